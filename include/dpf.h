@@ -1,0 +1,322 @@
+/*
+ * dpf.h -- C ABI of the data-path-fusion query library for MI355X (gfx950).
+ *
+ * One query pipeline = scan compressed column chunks -> decode -> filter ->
+ * hash-join probes -> group-by aggregation, run by ONE persistent HIP kernel
+ * with no intermediate results materialised (paper Section 3.1, the fused
+ * kernels #1..#3; Section 3.2, kernel fusion; Section 4.1, fused kernel
+ * composition).  A multi-kernel ("fragmented") execution of the same plan,
+ * the form the paper argues against (Section 5.1, the GiDP baseline), is kept
+ * beside it.
+ *
+ * Conventions for every call:
+ *  - Returns dpf_status: DPF_OK (0) or a negative DPF_ERR_* code.  On error,
+ *    out-parameters are left untouched and dpf_last_error() describes it.
+ *  - Nothing throws across this ABI and the library never aborts.
+ *  - Host arrays passed in are borrowed for the duration of the call only.
+ *  - Handles are reference counted: a plan retains its columns and hashes, a
+ *    result retains its plans; *_release drops one reference.
+ *  - A context is used by one host thread at a time.
+ *  - Device work is enqueued on the caller's stream (a hipStream_t passed as
+ *    dpf_stream; NULL is the null stream) and never synchronised inside the
+ *    call, except where a call's description says it synchronises.
+ *  - Device memory (HBM) and pinned, device-mapped host memory come from the
+ *    context's allocator (hipMalloc / hipHostMalloc when none is given).
+ */
+#ifndef DPF_H
+#define DPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dpf_status;
+enum {
+    DPF_OK = 0,
+    DPF_ERR_INVALID_ARG = -1,   /* bad handle, size, index or combination            */
+    DPF_ERR_OOM = -2,           /* an allocation failed                               */
+    DPF_ERR_HIP = -3,           /* a HIP runtime call failed                          */
+    DPF_ERR_UNSUPPORTED = -4,   /* valid, but outside what this build implements      */
+    DPF_ERR_OVERFLOW = -5,      /* an aggregate could exceed int64 (static bound)     */
+    DPF_ERR_CAPACITY = -6,      /* a device table ran out of room (reported by kernel) */
+    DPF_ERR_DUPLICATE_KEY = -7, /* a hash build met the same key twice                */
+    DPF_ERR_CORRUPT = -8,       /* a chunk or mini-block header is inconsistent        */
+    DPF_ERR_NOT_READY = -9      /* result read before its work was issued              */
+};
+
+typedef struct dpf_ctx_s* dpf_ctx;
+typedef struct dpf_column_s* dpf_column;
+typedef struct dpf_hash_s* dpf_hash;
+typedef struct dpf_plan_s* dpf_plan;
+typedef struct dpf_result_s* dpf_result;
+typedef void* dpf_stream; /* a hipStream_t */
+
+/* Thread-local description of the last error on this thread; valid until the
+ * next call on the thread. */
+const char* dpf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------ */
+enum { DPF_MEM_HBM = 0, DPF_MEM_HOST_MAPPED = 1 };
+
+/* Optional allocator.  alloc returns memory of the given kind (HBM, or pinned
+ * host memory that the device can address) or NULL; free releases it.  For
+ * DPF_MEM_HOST_MAPPED the returned pointer must be a host pointer that
+ * hipHostGetDevicePointer accepts. */
+typedef struct {
+    void* user;
+    void* (*alloc)(void* user, size_t bytes, int32_t kind);
+    void (*free)(void* user, void* p, int32_t kind);
+} dpf_allocator;
+
+/* device >= 0 selects a GPU; device == -1 makes a host-only context in which
+ * only encoding, column inspection and host decoding work (placement must be
+ * DPF_PLACE_HOST).  allocator may be NULL. */
+dpf_status dpf_ctx_create(int32_t device, const dpf_allocator* allocator, dpf_ctx* out);
+void dpf_ctx_destroy(dpf_ctx ctx);
+
+typedef struct {
+    int32_t device;
+    int32_t num_cus;           /* compute units                          */
+    int64_t lds_per_block;     /* bytes of LDS one workgroup may use     */
+    int64_t hbm_bytes;         /* device memory                          */
+    int64_t launches;          /* kernels this context has launched      */
+} dpf_ctx_info;
+dpf_status dpf_ctx_get_info(dpf_ctx ctx, dpf_ctx_info* out);
+
+/* ---------------------------------------------------------------------------
+ * Columns: type-specific compression into chunks of mini blocks (paper
+ * Section 3.4.1: mini blocks each preceded by a frame-of-reference base, bit
+ * width and offset; Section 3.4.2 and Figure 4: variable-length values and
+ * the row-id index; Section 4.2: the loader's page-offset, page-size and
+ * row-count side arrays).
+ *
+ * A column is split into chunks of chunk_rows rows (a multiple of 256; the
+ * paper's page) and each chunk into mini blocks of 256 values.  Encodings:
+ *   FOR    value = base + (packed bits), width per mini block 0..64 bits;
+ *   DELTA  value_i = anchor + sum over j <= i of (dmin + packed_j);
+ *   DICT   codes (ranks in the sorted distinct values) packed as FOR;
+ *   VARLEN string lengths packed as FOR + a contiguous byte heap.
+ * AUTO picks VARLEN for strings, DELTA for non-decreasing integers, else FOR.
+ * ------------------------------------------------------------------------ */
+enum { DPF_TYPE_I32 = 1, DPF_TYPE_I64 = 2, DPF_TYPE_STR = 3 };
+enum { DPF_ENC_AUTO = 0, DPF_ENC_FOR = 1, DPF_ENC_DELTA = 2, DPF_ENC_DICT = 3, DPF_ENC_VARLEN = 4 };
+enum { DPF_PLACE_HBM = 0, DPF_PLACE_HOST_MAPPED = 1, DPF_PLACE_HOST = 2 };
+
+/* I32/I64: values points to nrows int32_t / int64_t.  STR: str_offsets has
+ * nrows + 1 non-decreasing entries starting at 0 into str_bytes. */
+typedef struct {
+    int32_t type;
+    int64_t nrows;
+    const void* values;
+    const int64_t* str_offsets;
+    const uint8_t* str_bytes;
+} dpf_column_src;
+
+/* chunk_rows 0 means 65536.  placement HBM copies the encoded column to
+ * device memory; HOST_MAPPED keeps it in pinned host memory that kernels read
+ * directly over the host link; HOST keeps it on the host only (tests). */
+typedef struct {
+    int32_t encoding;
+    int32_t chunk_rows;
+    int32_t placement;
+    int32_t threads; /* encoder threads, 0 = hardware concurrency */
+} dpf_encode_opts;
+
+/* Encodes src into a new column.  Copies what it needs from src.  For HBM the
+ * upload is complete when the call returns. */
+dpf_status dpf_column_encode(dpf_ctx ctx, const dpf_column_src* src, const dpf_encode_opts* opts,
+                             dpf_column* out);
+
+typedef struct {
+    int32_t type, encoding, placement;
+    int32_t chunk_rows;
+    int64_t nrows;
+    int64_t nchunks;
+    int64_t nminiblocks;
+    int64_t compressed_bytes; /* bytes a full scan reads: packed data + mini-block headers
+                                 (+ dictionary, + string heap) */
+    int64_t min, max;         /* integer columns: value range (0, 0 when empty) */
+    int64_t ndict;            /* DICT: distinct values                          */
+    int64_t str_bytes;        /* VARLEN: heap bytes                             */
+} dpf_column_stats;
+dpf_status dpf_column_info(dpf_column col, dpf_column_stats* out);
+
+/* Per-chunk directory entry: the row-id index (row_start is the prefix sum of
+ * row counts) and the zone map (min/max of the chunk's values). */
+typedef struct {
+    int64_t row_start;
+    int64_t nrows;
+    int64_t byte_offset, byte_length; /* of the chunk's packed data (or heap, for VARLEN) */
+    int64_t min, max;
+} dpf_chunk_info;
+dpf_status dpf_column_chunk(dpf_column col, int64_t chunk, dpf_chunk_info* out);
+
+/* Host-side decode of the whole column (round-trip checks).  I32/I64: values
+ * receives nrows values of the column's type.  STR: str_offsets receives
+ * nrows + 1 offsets and str_bytes at most cap bytes.  Returns
+ * DPF_ERR_INVALID_ARG if cap is too small. */
+dpf_status dpf_column_decode(dpf_column col, void* values, int64_t* str_offsets, uint8_t* str_bytes,
+                             size_t cap);
+
+/* For tests of corruption handling: a host pointer to the column's array of
+ * mini-block word offsets (nminiblocks + 1 uint32), valid for HOST and
+ * HOST_MAPPED placement; writing to it is visible to later kernels. */
+dpf_status dpf_column_debug_offsets(dpf_column col, uint32_t** offsets);
+void dpf_column_release(dpf_column col);
+
+/* ---------------------------------------------------------------------------
+ * Predicates (conjunctive atoms; paper Section 3.1 and Section 4.1: filters
+ * and a LIKE-style string matcher evaluated inside the fused kernel)
+ * ------------------------------------------------------------------------ */
+enum {
+    DPF_OP_LT = 1, DPF_OP_LE, DPF_OP_GT, DPF_OP_GE, DPF_OP_EQ, DPF_OP_NE,
+    DPF_OP_BETWEEN,         /* a <= x <= b                                        */
+    DPF_OP_IN,              /* x equals one of in_values[0..n_in), n_in <= 64      */
+    DPF_OP_STR_CONTAINS_SEQ /* s1 occurs and s2 occurs at or after its end
+                               (LIKE '%s1%s2%'); 1 <= n1, n2 <= 32 bytes          */
+};
+typedef struct {
+    int32_t col; /* index into the column array of the enclosing description */
+    int32_t op;
+    int64_t a, b;
+    int32_t n_in;
+    const int64_t* in_values;
+    const uint8_t* s1;
+    int32_t n1;
+    const uint8_t* s2;
+    int32_t n2;
+} dpf_pred;
+
+/* ---------------------------------------------------------------------------
+ * Dimension hash tables (paper Section 3.1, Kernel #1: scan a dimension,
+ * filter it and build the hash table a later pipeline probes; Section 4.3:
+ * the build side must fit in GPU memory).
+ * ------------------------------------------------------------------------ */
+enum { DPF_HASH_AUTO = 0, DPF_HASH_LDS = 1, DPF_HASH_HBM = 2 };
+typedef struct {
+    int32_t ncols;
+    const dpf_column* cols;     /* dimension columns (same row count)          */
+    int32_t key_col;            /* unique among qualifying rows; values must fit
+                                   int32 and differ from INT32_MIN              */
+    int32_t npreds;
+    const dpf_pred* preds;      /* integer predicates over cols                */
+    int32_t npayloads;          /* 0..2 integer payload columns                 */
+    int32_t payload_cols[2];
+    int32_t placement;          /* where probes keep the table (AUTO: LDS when
+                                   it fits the per-workgroup LDS budget)       */
+} dpf_hash_desc;
+
+/* Builds an open-addressing table (power-of-two capacity, load <= 1/2) in HBM
+ * from the qualifying rows.  Synchronises the stream (the entry count sizes
+ * the table).  DPF_ERR_DUPLICATE_KEY if a key repeats. */
+dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf_stream stream, dpf_hash* out);
+
+typedef struct {
+    int64_t entries, capacity, bytes;
+    int32_t lds_eligible, placement;
+    int32_t npayloads;
+    int64_t key_min, key_max;
+    int64_t payload_min[2], payload_max[2];
+} dpf_hash_stats;
+dpf_status dpf_hash_info(dpf_hash h, dpf_hash_stats* out);
+void dpf_hash_release(dpf_hash h);
+
+/* ---------------------------------------------------------------------------
+ * Plans: scan(cols) -> filter(preds) -> probe(fk, hash)* -> group by keys ->
+ * aggregates (paper Section 3.1: the host generates the plan; Kernel #3
+ * probes and aggregates; the result returns in record form).
+ * ------------------------------------------------------------------------ */
+enum { DPF_REF_COL = 0, DPF_REF_PAYLOAD = 1 };
+typedef struct {
+    int32_t kind;  /* DPF_REF_COL: fact column idx; DPF_REF_PAYLOAD: payload idx of probe */
+    int32_t idx;
+    int32_t probe;
+} dpf_ref;
+
+/* A factor mul * ref + add (or add alone when has_ref is 0). */
+typedef struct {
+    int32_t has_ref;
+    dpf_ref ref;
+    int64_t mul, add;
+} dpf_term;
+
+enum { DPF_AGG_COUNT = 0, DPF_AGG_SUM = 1, DPF_AGG_AVG = 2 };
+/* COUNT -> one output column; SUM(product of terms) -> one; AVG -> two (sum,
+ * count): an exact average as a pair. */
+typedef struct {
+    int32_t op;
+    int32_t nterms; /* 1..3 for SUM and AVG */
+    dpf_term terms[3];
+} dpf_agg;
+
+typedef struct {
+    int32_t fk_col;
+    dpf_hash hash;
+} dpf_probe;
+
+typedef struct {
+    int32_t ncols;
+    const dpf_column* cols;  /* fact columns, all of the same table */
+    int32_t npreds;
+    const dpf_pred* preds;
+    int32_t nprobes;         /* probed in this order (put the most selective first) */
+    const dpf_probe* probes;
+    int32_t nkeys;
+    const dpf_ref* keys;
+    int32_t naggs;
+    const dpf_agg* aggs;
+} dpf_plan_desc;
+
+/* Validates the plan, proves every aggregate stays within int64 over the
+ * table (else DPF_ERR_OVERFLOW), sizes the group table and pre-allocates the
+ * per-plan device workspace and pinned result buffer, so that executing the
+ * plan allocates nothing and can be captured in a HIP graph. */
+dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf_plan* out);
+
+/* Device memory the plan itself holds (group table, workspace and the hash
+ * tables it probes), for admission control. */
+dpf_status dpf_plan_footprint(dpf_plan plan, size_t* hbm_bytes);
+void dpf_plan_release(dpf_plan plan);
+
+/* ---------------------------------------------------------------------------
+ * Execution
+ * ------------------------------------------------------------------------ */
+enum { DPF_MODE_FUSED = 0, DPF_MODE_FRAGMENTED = 1 };
+typedef struct {
+    int32_t mode;
+    int32_t wg_per_cu;       /* FUSED: workgroups per compute unit (0 = auto)          */
+    int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = 65536) */
+    int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto)     */
+} dpf_exec_opts;
+
+/* Enqueues n >= 1 plans on stream.  FUSED runs them all in ONE launch of the
+ * persistent kernel, which claims (plan, row range) work items from a device
+ * queue; FRAGMENTED runs each plan as a sequence of separate kernels with
+ * materialised intermediates (it allocates on first use and is not meant for
+ * graph capture).  FUSED with n <= 64 allocates nothing and is
+ * graph-capturable.  A plan must not be in two executions at once.  *out
+ * receives a result handle that is readable after the stream has
+ * synchronised. */
+dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
+                       dpf_stream stream, dpf_result* out);
+
+/* Reads plan i's records after the work has completed (the caller
+ * synchronises the stream).  Rows are int64: group key values, then the
+ * aggregate columns, one row per non-empty group, ascending by key.  Returns
+ * the device-reported status (e.g. DPF_ERR_CAPACITY, DPF_ERR_CORRUPT) and no
+ * rows when the kernel reported an error.  Each call decodes the buffer anew
+ * (so a result captured in a graph can be read after every replay); *rows
+ * stays valid until the next call on the same result or its release. */
+dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* ncols,
+                          const int64_t** rows);
+void dpf_result_release(dpf_result res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPF_H */

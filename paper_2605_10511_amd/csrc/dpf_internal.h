@@ -1,0 +1,174 @@
+// dpf_internal.h -- descriptors shared by the host runtime and the gfx950
+// kernels.  A plan is flattened into one DevQuery in device memory; the
+// persistent kernel reads it with scalar (wave-uniform) loads.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace dpf {
+
+constexpr int kMB = 256;          // values per mini block
+constexpr int kWave = 64;         // CDNA wavefront
+constexpr int kWaves = 4;         // waves per workgroup
+constexpr int kBlock = kWave * kWaves;
+constexpr int kMaxCols = 16;      // fact columns per plan
+constexpr int kMaxPreds = 12;     // predicate atoms per plan
+constexpr int kMaxProbes = 4;     // probes per plan
+constexpr int kMaxSlots = 8;      // values carried per surviving row
+constexpr int kMaxKeys = 4;       // group-by keys
+constexpr int kMaxAccs = 12;      // accumulators (count + sums)
+constexpr int kMaxTerms = 3;      // factors per aggregate product
+constexpr int kMaxIn = 64;        // IN-list values per plan
+constexpr int kMaxWord = 32;      // bytes per string-predicate word
+constexpr int kMaxBatch = 64;     // plans per fused launch
+constexpr int kMaxHashCols = 8;   // dimension columns per hash build
+constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
+constexpr int64_t kMaxGroups = int64_t(1) << 22;  // direct-indexed group table limit
+constexpr int kStrHeapCap = 11264;  // per-wave LDS bytes staging one mini block's strings
+constexpr int32_t kEmptyKey = INT32_MIN;
+
+enum : int32_t { ENC_FOR = 1, ENC_DELTA = 2, ENC_DICT = 3, ENC_VARLEN = 4 };
+
+// Device view of one encoded column (all arrays indexed by global mini block).
+struct DevCol {
+    const int64_t* base;    // [nmb] FOR base | DELTA anchor | DICT code base | VARLEN min length
+    const uint32_t* woff;   // [nmb + 1] first word of each mini block's packed data
+    const uint32_t* words;  // packed values, LSB first, value i at bit i * width
+    const int64_t* dmin;    // DELTA: [nmb] minimum first difference
+    const uint64_t* hoff;   // VARLEN: [nmb + 1] byte offset of the mini block's strings
+    const uint8_t* heap;    // VARLEN: string bytes (padded)
+    const int64_t* dict;    // DICT: [ndict] sorted distinct values
+    int64_t nrows;
+    uint64_t heap_bytes;
+    uint32_t nwords;
+    int32_t nmb;
+    int32_t enc;
+    int32_t ndict;
+};
+
+enum : int32_t { PK_RANGE = 1, PK_NE = 2, PK_INMASK = 3, PK_INLIST = 4, PK_STR = 5, PK_FALSE = 6 };
+
+// One conjunctive atom, already rewritten into the column's code space
+// (dictionary columns compare codes).
+struct DevPred {
+    int32_t col;
+    int32_t kind;
+    int64_t lo, hi;     // RANGE: lo <= x <= hi; NE: x != lo
+    uint64_t mask;      // INMASK: bit c set -> code c qualifies (codes < 64)
+    int32_t in_off;     // INLIST: values in_vals[in_off .. in_off + n_in)
+    int32_t n_in;
+    int32_t n1, n2;     // STR: word lengths
+    uint8_t s1[kMaxWord];
+    uint8_t s2[kMaxWord];
+};
+
+// Open-addressing table: int32 keys (kEmptyKey = free), payload arrays
+// follow the key array in the same allocation.
+struct DevHash {
+    const int32_t* keys;
+    const void* pay[2];
+    uint32_t cap_mask;
+    int32_t log2cap;
+    int32_t npay;
+    int32_t pay64[2];   // payload k stored as int64 (else int32)
+    int32_t lds_off;    // >= 0: byte offset of the workgroup's LDS copy
+    uint32_t bytes;     // keys + payloads
+};
+
+struct DevProbe {
+    int32_t fk_col;
+    int32_t pay_slot[2];  // value slot receiving payload k (-1: unused)
+    DevHash h;
+};
+
+struct DevLoad { int32_t col, slot, dict_val, pad; };  // fact column -> value slot (DICT: code or value)
+struct DevKey { int32_t slot; int32_t pad; int64_t min, card, stride; };
+struct DevTerm { int32_t slot; int32_t pad; int64_t mul, add; };  // slot < 0: constant add
+struct DevAcc { int32_t nterms; int32_t pad; DevTerm t[kMaxTerms]; };
+
+enum : uint32_t { ST_CORRUPT = 1u, ST_CAPACITY = 2u, ST_UNSUPPORTED = 4u, ST_DUPLICATE = 8u };
+
+struct DevQuery {
+    int64_t nrows;
+    int32_t nmb;
+    int32_t ncols;
+    DevCol cols[kMaxCols];
+    int32_t npreds;  // integer atoms first, then string atoms
+    int32_t nint_preds;
+    DevPred preds[kMaxPreds];
+    int64_t in_vals[kMaxIn];
+    int32_t nprobes;
+    int32_t nloads;
+    DevProbe probes[kMaxProbes];
+    DevLoad loads[kMaxSlots];
+    int32_t nkeys;
+    int32_t nacc;    // accumulator 0 is the row count
+    DevKey keys[kMaxKeys];
+    DevAcc accs[kMaxAccs];
+    int64_t ngroups;
+    int64_t* agg;        // device [ngroups * nacc], zero between executions
+    int32_t agg_lds;     // accumulate in the workgroup's LDS table first
+    int32_t agg_lds_off; // byte offset of that table
+    int32_t lds_shared;  // LDS bytes of this plan's shared area (hashes + table)
+    int32_t has_str;
+    uint32_t* status;    // device status bits (ST_*)
+    int64_t* host_out;   // device address of the pinned output: [status, nrec, records...]
+};
+
+struct BatchArgs {
+    const DevQuery* q[kMaxBatch];
+    int32_t item_start[kMaxBatch + 1];
+    int32_t nq;
+    int32_t mb_per_item;
+    uint32_t* counters;   // [0] work-queue head, [1] finished workgroups
+    int32_t lds_shared;   // max lds_shared over the batch
+    int32_t str_stage;    // per-wave string staging present
+};
+
+// Hash build over a dimension table.
+struct HashBuildArgs {
+    DevCol cols[kMaxHashCols];
+    int32_t ncols;
+    int32_t npreds;
+    DevPred preds[kMaxHashPreds];
+    int64_t in_vals[kMaxIn];
+    int32_t key_col;
+    int32_t npay;
+    int32_t pay_col[2];
+    int32_t nmb;
+    int32_t pad;
+    int64_t nrows;
+    // outputs
+    unsigned long long* count;  // qualifying rows
+    long long* mm;              // [0..1] key min/max, [2..5] payload min/max
+    uint32_t* status;
+    // insert pass
+    int32_t* keys;
+    void* pay[2];
+    int32_t pay64[2];
+    uint32_t cap_mask;
+    int32_t log2cap;
+};
+
+// Launchers (kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_fused(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_hash_count(const HashBuildArgs* d_args, int grid, hipStream_t s);
+hipError_t launch_hash_insert(const HashBuildArgs* d_args, int grid, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+
+// Fragmented (multi-kernel) execution of one plan.
+struct FragBuffers {
+    int64_t* dec[kMaxCols];      // decoded integer columns (codes for DICT)
+    int64_t* str_off[kMaxCols];  // decoded string offsets [nrows + 1]
+    uint8_t* str_bytes[kMaxCols];
+    uint8_t* flags;              // [nrows]
+    int32_t* rows[2];            // ping-pong row lists [nrows]
+    int64_t* pay[2][2 * kMaxProbes];  // payload arrays aligned with the row lists
+    unsigned long long* counts;  // [kMaxProbes + 2] list lengths
+};
+// Returns the number of kernels launched, or -1 on a launch error.
+int run_fragmented(const DevQuery* d_q, const DevQuery& h_q, const FragBuffers& fb, hipStream_t s);
+
+}  // namespace dpf

@@ -1,0 +1,243 @@
+"""GPU parity: the library's fused and fragmented executions against the CPU
+oracle, bit-exactly, on seeded inputs spanning several mini blocks, chunks
+and a ragged tail; plus hand-computed cases, batching, host-mapped placement,
+graph replay and device-reported errors."""
+import numpy as np
+import pytest
+
+import oracle
+from datagen import workloads as W
+from tests import gpu_util as G
+from tests.test_oracle_pins import _random_instance, _random_query
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2605_10511_amd import dpf
+    assert torch.cuda.is_available()
+    return dpf.Context(0)
+
+
+def test_hand_cases(ctx, hand_cases):
+    from paper_2605_10511_amd import dpf
+    tables, cases = hand_cases
+    db = G.make_db(ctx, tables, chunk_rows=256)
+    for case in cases:
+        G.say("hand case", case["name"])
+        if "error" in case:
+            want = {"duplicate": dpf.DPF_ERR_DUPLICATE_KEY, "overflow": dpf.DPF_ERR_OVERFLOW}[case["error"]]
+            with pytest.raises(dpf.DpfError) as e:
+                G.run_gpu(db, case["query"])
+            assert e.value.code == want, case["name"]
+            continue
+        for mode in ("FUSED", "FRAGMENTED"):
+            got = G.run_gpu(db, case["query"], mode=mode)
+            assert got.tolist() == case["expect"], (case["name"], mode)
+
+
+def test_filter_aggregate_1m(ctx):
+    G.say("filter-aggregate 1,000,000 rows")
+    t = W.fa_table(1_000_000, seed=1)
+    spec = W.fa_query()
+    want = oracle.run(spec, {"fact": t})
+    db = G.make_db(ctx, {"fact": t}, {"fact": W.FA_ENCODINGS})
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, mode)
+    for rpi, wg in ((256, 1), (16384, 2), (131072, 4)):
+        G.assert_same(G.run_gpu(db, spec, rows_per_item=rpi, wg_per_cu=wg), want, f"items {rpi} wg {wg}")
+
+
+@pytest.mark.parametrize("chunk_rows", [256, 65536])
+def test_filter_aggregate_ragged(ctx, chunk_rows):
+    G.say("filter-aggregate ragged, chunk", chunk_rows)
+    t = W.fa_table(70_001, seed=5)
+    for spec in (W.fa_query(), W.fa_query(date_lt=100, disc_lo=0, disc_hi=10, qty_lt=51),
+                 W.fa_query(date_lt=0)):
+        want = oracle.run(spec, {"fact": t})
+        db = G.make_db(ctx, {"fact": t}, {"fact": W.FA_ENCODINGS}, chunk_rows=chunk_rows)
+        for mode in ("FUSED", "FRAGMENTED"):
+            G.assert_same(G.run_gpu(db, spec, mode=mode), want, mode)
+
+
+def test_wide_strings(ctx):
+    G.say("wide table with strings, 300,000 rows")
+    t = W.wide_table(300_000, seed=2)
+    w1, w2, vocab = W.wide_words(2)
+    db = G.make_db(ctx, {"fact": t}, {"fact": W.WIDE_ENCODINGS})
+    for (a, b) in ((w1, w2), (w2, w1), (vocab[5][:2], vocab[9][:1]), (b"a", b"e"), (b" ", b" ")):
+        spec = W.wide_query(a, b)
+        want = oracle.run(spec, {"fact": t})
+        for mode in ("FUSED", "FRAGMENTED"):
+            G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{a}/{b} {mode}")
+
+
+def test_long_strings_fall_back(ctx):
+    """Mini blocks whose strings exceed the LDS staging area take the
+    lane-per-row path."""
+    G.say("long strings")
+    from tests.conftest import to_strings
+    rng = np.random.default_rng(4)
+    n = 2000
+    items = []
+    for i in range(n):
+        L = int(rng.integers(0, 300))
+        s = bytes(rng.choice(np.frombuffer(b"ab c", np.uint8), L))
+        items.append(s)
+    t = {"s": to_strings(items), "g": (np.arange(n) % 3).astype(np.int32)}
+    db = G.make_db(ctx, {"t": t})
+    for a, b in ((b"ab", b"c"), (b"abc", b"ba"), (b"a", b"a"), (b"c c", b"b")):
+        spec = {"fact": "t", "filters": [{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": a, "s2": b}],
+                "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
+        want = oracle.run(spec, {"t": t})
+        for mode in ("FUSED", "FRAGMENTED"):
+            G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{a}/{b} {mode}")
+
+
+@pytest.mark.parametrize("variant", ["3a", "3b"])
+def test_star_join_small(ctx, variant):
+    G.say("star join small", variant)
+    # at 1/100 of the dimension sizes the 1/1000 part filter leaves almost
+    # no fact rows, so the small test filters part by category (1/25)
+    dims = W.sj_dims(seed=3, scale=0.01)
+    fact = W.sj_fact(1_000_000, seed=3, dims=dims)
+    spec = (W.sj_query(part_category=4, date_dow=2) if variant == "3a"
+            else W.sj_query(date_dow=None, part_category=4))
+    tables = {"lo": fact, **dims}
+    want = oracle.run(spec, tables)
+    assert len(want) > 0
+    db = G.make_db(ctx, tables)
+    for placements in (None, ["HBM", "LDS", "LDS", "HBM"], ["HBM"] * 4, ["LDS"] * 4):
+        for mode in ("FUSED", "FRAGMENTED"):
+            got = G.run_gpu(db, spec, mode=mode, placements=placements)
+            G.assert_same(got, want, f"{placements} {mode}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_queries(ctx, seed):
+    G.say("random queries seed", seed)
+    from paper_2605_10511_amd import dpf
+    rng = np.random.default_rng(5000 + seed)
+    tables = _random_instance(rng, n=3000 + 97 * seed)
+    db = G.make_db(ctx, tables, chunk_rows=512)
+    for _ in range(4):
+        spec = _random_query(rng)
+        try:
+            want = oracle.run(spec, tables)
+        except oracle.OracleError as e:
+            if e.code == oracle.ERR_DUPLICATE:
+                continue
+            raise
+        for mode in ("FUSED", "FRAGMENTED"):
+            try:
+                got = G.run_gpu(db, spec, mode=mode)
+            except dpf.DpfError as e:
+                # the static int64 bound may refuse a plan the data never overflows
+                assert e.code == dpf.DPF_ERR_OVERFLOW, e
+                continue
+            G.assert_same(got, want, f"{spec} {mode}")
+
+
+def test_batch_equals_solo(ctx):
+    G.say("batched plans in one launch")
+    import torch
+    from paper_2605_10511_amd import dpf
+    fa = W.fa_table(200_000, seed=8)
+    fa2 = W.fa_table(35_000, seed=9)
+    dims = W.sj_dims(seed=3, scale=0.01)
+    lo = W.sj_fact(150_000, seed=10, dims=dims)
+    tables = {"fa": fa, "fa2": fa2, "lo": lo, **dims}
+    db = G.make_db(ctx, tables, {"fa": W.FA_ENCODINGS, "fa2": W.FA_ENCODINGS})
+    specs = [W.fa_query("fa"), W.fa_query("fa2", date_lt=900, disc_lo=2, disc_hi=4, qty_lt=40),
+             W.sj_query(part_category=3, date_dow=None), W.sj_query(part_attr=5),
+             W.fa_query("fa", date_lt=2555, disc_lo=0, disc_hi=10, qty_lt=51)]
+    wants = [oracle.run(s, tables) for s in specs]
+    plans = [db.plan(s) for s in specs]
+    for rpi in (0, 16384):
+        res = dpf.execute(ctx, plans, rows_per_item=rpi)
+        torch.cuda.synchronize()
+        for i, w in enumerate(wants):
+            G.assert_same(res.get(i), w, f"batch plan {i}")
+        res.release()
+    for i, p in enumerate(plans):
+        res = dpf.execute(ctx, [p])
+        torch.cuda.synchronize()
+        G.assert_same(res.get(0), wants[i], f"solo plan {i}")
+        res.release()
+
+
+def test_host_mapped_equals_hbm(ctx):
+    G.say("host-mapped placement")
+    t = W.fa_table(300_000, seed=11)
+    spec = W.fa_query()
+    want = oracle.run(spec, {"fact": t})
+    for place in ("HBM", "HOST_MAPPED"):
+        db = G.make_db(ctx, {"fact": t}, {"fact": W.FA_ENCODINGS}, placement=place)
+        for mode in ("FUSED", "FRAGMENTED"):
+            G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{place} {mode}")
+
+
+def test_corrupt_header_reported(ctx):
+    G.say("corrupt mini-block header")
+    from paper_2605_10511_amd import dpf
+    t = W.fa_table(20_000, seed=12)
+    spec = W.fa_query()
+    db = G.make_db(ctx, {"fact": t}, {"fact": W.FA_ENCODINGS}, placement="HOST_MAPPED")
+    offs = db.tables["fact"]["quantity"].debug_offsets()
+    saved = offs[5]
+    offs[5] = saved + 3  # no longer a whole number of 8-word groups
+    with pytest.raises(dpf.DpfError) as e:
+        G.run_gpu(db, spec)
+    assert e.value.code == dpf.DPF_ERR_CORRUPT
+    offs[5] = saved
+    G.assert_same(G.run_gpu(db, spec), oracle.run(spec, {"fact": t}), "after repair")
+
+
+def test_hash_stats_and_duplicates(ctx):
+    G.say("hash build stats")
+    from paper_2605_10511_amd import dpf
+    dims = W.sj_dims(seed=3, scale=0.01)
+    cols = {c: dpf.Column(ctx, v) for c, v in dims["part"].items()}
+    h = dpf.Hash(ctx, cols, "p_partkey", [{"col": "p_category", "op": "EQ", "value": 7}], ["p_brand"])
+    s = h.info()
+    m = dims["part"]["p_category"] == 7
+    assert s.entries == int(m.sum())
+    assert s.capacity >= 2 * s.entries and s.capacity & (s.capacity - 1) == 0
+    assert s.payload_min[0] == dims["part"]["p_brand"][m].min()
+    assert s.payload_max[0] == dims["part"]["p_brand"][m].max()
+    dup = {"k": dpf.Column(ctx, np.array([1, 2, 3, 2], np.int32))}
+    with pytest.raises(dpf.DpfError) as e:
+        dpf.Hash(ctx, dup, "k", [], [])
+    assert e.value.code == dpf.DPF_ERR_DUPLICATE_KEY
+
+
+def test_graph_replay(ctx):
+    G.say("graph capture and replay")
+    import torch
+    from paper_2605_10511_amd import dpf
+    t = W.fa_table(500_000, seed=13)
+    spec = W.fa_query()
+    want = oracle.run(spec, {"fact": t})
+    db = G.make_db(ctx, {"fact": t}, {"fact": W.FA_ENCODINGS})
+    plan = db.plan(spec)
+    res = dpf.execute(ctx, [plan])  # warm (sets the LDS layout once)
+    torch.cuda.synchronize()
+    G.assert_same(res.get(0), want, "eager")
+    res.release()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            r = dpf.execute(ctx, [plan], stream=s)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        G.assert_same(r.get(0), want, f"replay {k}")
+        res = dpf.execute(ctx, [plan])
+        torch.cuda.synchronize()
+        G.assert_same(res.get(0), want, f"eager after replay {k}")
+        res.release()
+    r.release()
