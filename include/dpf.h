@@ -290,8 +290,9 @@ enum { DPF_MODE_FUSED = 0, DPF_MODE_FRAGMENTED = 1 };
 typedef struct {
     int32_t mode;
     int32_t wg_per_cu;       /* FUSED: workgroups per compute unit (0 = auto)          */
-    int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = 65536) */
+    int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = 16384) */
     int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto)     */
+    int32_t waves_per_wg;    /* FUSED: 4, 8 or 16 waves per workgroup (0 = auto)       */
 } dpf_exec_opts;
 
 /* Enqueues n >= 1 plans on stream.  FUSED runs them all in ONE launch of the

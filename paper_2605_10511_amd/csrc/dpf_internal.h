@@ -124,6 +124,7 @@ struct BatchArgs {
     uint32_t* counters;   // [0] work-queue head, [1] finished workgroups
     int32_t lds_shared;   // max lds_shared over the batch
     int32_t str_stage;    // per-wave string staging present
+    int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate)
 };
 
 // Hash build over a dimension table.
@@ -152,7 +153,10 @@ struct HashBuildArgs {
 };
 
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.
-hipError_t launch_fused(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+// waves: 4, 8 or 16 waves per workgroup.
+hipError_t launch_fused(const BatchArgs& a, int waves, int grid, size_t lds_bytes, hipStream_t s);
+// Per-wave LDS the fused kernel needs (survivor queue, string row offsets).
+size_t fused_wave_area_bytes(bool str, bool pend);
 hipError_t launch_hash_count(const HashBuildArgs* d_args, int grid, hipStream_t s);
 hipError_t launch_hash_insert(const HashBuildArgs* d_args, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -3,12 +3,14 @@
 //  * fused_kernel: ONE persistent kernel per launch runs whole query
 //    pipelines (paper Section 3.2 and Section 4.1 "Fused kernel
 //    composition"): each workgroup claims (plan, mini-block range) work
-//    items from a device queue, its four waves each take one 256-row mini
-//    block at a time, decode the referenced columns straight from where the
-//    chunks rest (HBM or pinned host memory mapped into the device), filter,
-//    probe dimension hash tables (LDS copies for small ones), aggregate into
-//    a per-workgroup LDS table, and the last workgroup to finish writes the
-//    records to the host buffer -- nothing is materialised in between.
+//    items from a device queue; its waves each take one 256-row mini block at
+//    a time, decode the referenced columns straight from where the chunks
+//    rest (HBM or pinned host memory mapped into the device), filter, and
+//    queue the surviving row ids in LDS; full batches of 64 survivors are
+//    probed against the dimension hash tables (LDS copies for small ones) and
+//    aggregated into a per-workgroup LDS table.  The last workgroup to finish
+//    writes the records to the host buffer -- nothing is materialised in
+//    between.
 //  * hash_count / hash_insert: the build side (Section 3.1, Kernel #1).
 //  * frag_*: the same plan as separate kernels with materialised
 //    intermediates (Section 5.1, the multi-kernel baseline).
@@ -22,6 +24,10 @@
 
 namespace dpf {
 namespace {
+
+constexpr int kPendCap = 320;   // per-wave survivor queue (64 pending + one mini block)
+constexpr int kSegIters = 8;    // 16-byte string loads per lane per segment (8 KB per wave)
+constexpr int kCandCap = 256;   // per-wave queue of verified string-predicate hits
 
 // ---------------------------------------------------------------------------
 // Wave helpers
@@ -184,33 +190,21 @@ __device__ __forceinline__ uint32_t eval_int_pred(const DevPred& p, const int64_
 
 // ---------------------------------------------------------------------------
 // String predicate "s1 then s2" (LIKE '%s1%s2%', paper Section 4.1) over one
-// mini block, byte-parallel on an LDS copy of the mini block's heap.
+// mini block, byte-parallel.
 //
-// Each lane scans 4-byte words of the staged heap and flags every position
-// where the first two bytes of a word match (a SWAR zero-byte test); flagged
-// positions are verified, mapped to their row by binary search over the row
-// offsets, and recorded as the row's leftmost s1 start and rightmost s2
-// start.  A row matches iff rightmost_s2 >= leftmost_s1 + |s1|.
+// The mini block's heap is read into registers with 16-byte loads: each lane
+// holds four consecutive words, and the two words after them come from the
+// next lane by a lane shift.  At every byte position the 4-byte window is
+// compared with the first 4 bytes of s1 and of s2 (three byte-aligns and
+// eight compares per word; the hit masks combine in scalar registers), so a
+// chance match costs nothing until a whole 4-byte prefix agrees.  The rare
+// hits are checked against 8 bytes taken from the same registers (the rest
+// of a longer word from memory), queued, mapped to their row by binary
+// search over the row offsets (LDS), and kept as the row's leftmost s1 start
+// and rightmost s2 start.  A row matches iff rightmost s2 >= leftmost s1 +
+// |s1|: the leftmost s1 leaves the most room for s2, the rightmost s2 is the
+// likeliest to follow it.
 // ---------------------------------------------------------------------------
-struct StrLds {
-    uint32_t* offs;    // [257] row start offsets within the mini block's heap
-    uint32_t* first1;  // [256] leftmost s1 start (0xffffffff: none)
-    uint32_t* last2;   // [256] rightmost s2 start + 1 (0: none)
-    uint32_t* heapw;   // staged heap words
-};
-
-__device__ __forceinline__ uint32_t zero_byte_flags(uint32_t z) {
-    return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
-}
-
-__device__ __forceinline__ uint32_t rep4(uint8_t c) { return 0x01010101u * c; }
-
-__device__ __forceinline__ bool str_eq_lds(const uint8_t* hb, uint32_t q, const uint8_t* w, int n) {
-    for (int i = 2; i < n; ++i)
-        if (hb[q + i] != w[i]) return false;
-    return true;
-}
-
 __device__ __forceinline__ int row_of(const uint32_t* offs, uint32_t p) {
     int lo = 0, hi = 255;  // largest r with offs[r] <= p
     while (lo < hi) {
@@ -220,102 +214,197 @@ __device__ __forceinline__ int row_of(const uint32_t* offs, uint32_t p) {
     return lo;
 }
 
+__device__ __forceinline__ bool bytes_eq(const uint8_t* s, const uint8_t* w, int from, int n) {
+    for (int i = from; i < n; ++i)
+        if (s[i] != w[i]) return false;
+    return true;
+}
+
+// Does s[from, n) contain w (length nw)?
+__device__ bool contains_from(const uint8_t* s, uint32_t from, uint32_t n, const uint8_t* w, int nw) {
+    for (uint32_t q = from; q + (uint32_t)nw <= n; ++q)
+        if (s[q] == w[0] && bytes_eq(s + q, w, 1, nw)) return true;
+    return false;
+}
+
+// LIKE '%s1%s2%' on one string where it rests (fragmented path).
 __device__ bool contains_seq_global(const uint8_t* s, uint32_t n, const DevPred& p) {
-    uint32_t n1 = p.n1, n2 = p.n2;
-    if (n < n1) return false;
-    for (uint32_t a = 0; a + n1 <= n; ++a) {
-        bool e = true;
-        for (uint32_t i = 0; i < n1 && e; ++i) e = s[a + i] == p.s1[i];
-        if (!e) continue;
-        for (uint32_t b = a + n1; b + n2 <= n; ++b) {
-            bool f = true;
-            for (uint32_t i = 0; i < n2 && f; ++i) f = s[b + i] == p.s2[i];
-            if (f) return true;
-        }
-        return false;  // the leftmost s1 leaves the most room for s2
+    for (uint32_t a = 0; a + (uint32_t)p.n1 <= n; ++a) {
+        if (s[a] != p.s1[0] || !bytes_eq(s + a, p.s1, 1, p.n1)) continue;
+        return contains_from(s, a + p.n1, n, p.s2, p.n2);  // leftmost s1 is optimal
     }
     return false;
 }
 
+struct StrPattern {
+    uint64_t p8, m8;  // first min(n, 8) bytes, little endian, and their mask
+};
+
+__device__ __forceinline__ StrPattern make_pattern(const uint8_t* w, int n) {
+    StrPattern P;
+    P.p8 = *reinterpret_cast<const uint64_t*>(w);  // bytes past n are zero
+    P.m8 = n >= 8 ? ~uint64_t(0) : ((uint64_t(1) << (8 * n)) - 1);
+    P.p8 &= P.m8;
+    return P;
+}
+
+struct StrLds {
+    uint32_t* offs;    // [257] row start offsets within the mini block's heap
+    uint32_t* first1;  // [256] leftmost s1 start (0xffffffff: none)
+    uint32_t* last2;   // [256] rightmost s2 start + 1 (0: none)
+    uint32_t* cand;    // [kCandCap] verified hits: pos << 2 | is_s1 | is_s2 << 1
+};
+
+// Maps the queued hits to their rows (binary search over the row offsets,
+// one hit per lane) and records leftmost s1 / rightmost s2 starts.
+__device__ __forceinline__ void resolve_hits(const StrLds& L, int ncand, const DevPred& p, const uint8_t* hs, int lane) {
+    wave_lds_sync();
+    for (int j = lane; j < ncand; j += kWave) {
+        const uint32_t e = L.cand[j], pos = e >> 2;
+        const int r = row_of(L.offs, pos);
+        const uint32_t rend = L.offs[r + 1];
+        if ((e & 1u) && pos + (uint32_t)p.n1 <= rend && (p.n1 <= 8 || bytes_eq(hs + pos, p.s1, 8, p.n1)))
+            atomicMin(&L.first1[r], pos);
+        if ((e & 2u) && pos + (uint32_t)p.n2 <= rend && (p.n2 <= 8 || bytes_eq(hs + pos, p.s2, 8, p.n2)))
+            atomicMax(&L.last2[r], pos + 1);
+    }
+    wave_lds_sync();
+}
+
 // Returns the 4-bit match mask of the lane's rows; clears ok on corruption.
-__device__ uint32_t eval_str_pred(const DevCol& c, const DevPred& p, int m, int lane, int nvalid,
-                                  const StrLds& L, bool& ok) {
+// kMasked: some word is shorter than 4 bytes, so 4-byte windows are masked.
+template <bool kMasked>
+__device__ __forceinline__ uint32_t str_pred(const DevCol& c, const DevPred& p, int m, int lane, int nvalid,
+                                             const StrLds& L, bool& ok) {
+    uint32_t* const offs = L.offs;
     MbHdr h = mb_hdr(c, m);
-    uint64_t h0 = c.hoff[m], h1 = c.hoff[m + 1];
-    bool hok = h.ok && h0 <= h1 && h1 <= c.heap_bytes && (h1 - h0) < (uint64_t(1) << 31);
-    if (!hok) { ok = false; return 0; }
-    uint32_t len[4];
+    const uint64_t h0 = c.hoff[m], h1 = c.hoff[m + 1];
+    if (!(h.ok && h0 <= h1 && h1 <= c.heap_bytes && (h1 - h0) < (uint64_t(1) << 30))) {
+        ok = false;
+        return 0;
+    }
+    const uint64_t a0 = h0 & ~uint64_t(15);
+    const uint32_t s0 = (uint32_t)(h0 - a0);
+    const uint4* g = reinterpret_cast<const uint4*>(c.heap + a0);
+    // Issue the first heap segment's loads before the length scan.
+    uint4 W[kSegIters];
+    const uint32_t span0 = s0 + (uint32_t)(h1 - h0);
+    const uint32_t nvec = (span0 + 15u) >> 4;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int i = 64 * k + lane;
+    for (int it = 0; it < kSegIters; ++it) {
+        uint32_t v = it * kWave + lane;
+        W[it] = v <= nvec ? g[v] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // Row offsets: lane l takes rows 4l..4l+3, so one wave scan suffices.
+    uint32_t len[4], lsum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int i = 4 * lane + j;
         uint32_t u = h.b ? (uint32_t)bits_at(h.w, (uint32_t)i * (uint32_t)h.b, h.b) : 0u;
-        len[k] = i < nvalid ? (uint32_t)h.base + u : 0u;
+        len[j] = i < nvalid ? (uint32_t)h.base + u : 0u;
+        lsum += len[j];
     }
-    uint32_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        uint32_t s = wave_incl_scan_u32(len[k], lane);
-        L.offs[64 * k + lane] = carry + s - len[k];
-        carry += __builtin_amdgcn_readlane(s, 63);
+    const uint32_t incl = wave_incl_scan_u32(lsum, lane);
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+    {
+        uint32_t o = incl - lsum;
+        uint4 ov;
+        ov.x = o;
+        ov.y = o + len[0];
+        ov.z = ov.y + len[1];
+        ov.w = ov.z + len[2];
+        reinterpret_cast<uint4*>(offs)[lane] = ov;
+        reinterpret_cast<uint4*>(L.first1)[lane] = make_uint4(~0u, ~0u, ~0u, ~0u);
+        reinterpret_cast<uint4*>(L.last2)[lane] = make_uint4(0u, 0u, 0u, 0u);
     }
-    const uint32_t total = carry;
-    if (lane == 0) L.offs[256] = total;
+    if (lane == 0) offs[256] = total;
     if ((uint64_t)total != h1 - h0) { ok = false; return 0; }
 
-    uint32_t res = 0;
-    if (total + 8u > (uint32_t)kStrHeapCap) {
-        // Mini block too large for the staging area: lane-per-row scan of
-        // the bytes where they rest.
-        wave_lds_sync();
-        for (int k = 0; k < 4; ++k) {
-            int i = 64 * k + lane;
-            if (i < nvalid) {
-                uint32_t o = L.offs[i];
-                res |= (uint32_t)contains_seq_global(c.heap + h0 + o, L.offs[i + 1] - o, p) << k;
+    const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
+    const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;  // first 4 bytes
+    const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
+    const uint8_t* hs = c.heap + h0;
+    int ncand = 0;
+    for (uint32_t base = 0;; base += kSegIters * kWave) {
+        // Hot loop: bit (4 * it + wd) of hits marks a word of the lane whose
+        // 4-byte window matched a prefix at one of its byte positions.
+        uint32_t hits = 0;
+#pragma unroll
+        for (int it = 0; it < kSegIters; ++it) {
+            const uint4 w = W[it];
+            uint32_t nx = __shfl_down(w.x, 1u, kWave);
+            if (it + 1 < kSegIters) {
+                const uint32_t lx = __builtin_amdgcn_readlane(W[it + 1 < kSegIters ? it + 1 : it].x, 0);
+                if (lane == 63) nx = lx;
+            } else {
+                const uint32_t v = base + kSegIters * kWave;
+                if (lane == 63) nx = v <= nvec ? g[v].x : 0u;
+            }
+            const uint32_t e[5] = {w.x, w.y, w.z, w.w, nx};
+#pragma unroll
+            for (int wd = 0; wd < 4; ++wd) {
+                const uint32_t w0 = e[wd];
+                const uint32_t w1 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 8);
+                const uint32_t w2 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 16);
+                const uint32_t w3 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 24);
+                bool hit;
+                if (kMasked)
+                    hit = ((w0 & k1) == q1) | ((w1 & k1) == q1) | ((w2 & k1) == q1) | ((w3 & k1) == q1) |
+                          ((w0 & k2) == q2) | ((w1 & k2) == q2) | ((w2 & k2) == q2) | ((w3 & k2) == q2);
+                else
+                    hit = (w0 == q1) | (w1 == q1) | (w2 == q1) | (w3 == q1) | (w0 == q2) | (w1 == q2) |
+                          (w2 == q2) | (w3 == q2);
+                hits |= hit ? (1u << (4 * it + wd)) : 0u;
             }
         }
-        return res;
-    }
-
-    // Stage the heap bytes [h0, h1) into LDS as whole words (plus one spare
-    // word so every position can read its successor).
-    const uint32_t s0 = (uint32_t)(h0 & 3u);
-    const uint32_t* g = reinterpret_cast<const uint32_t*>(c.heap) + (h0 >> 2);
-    const uint32_t nw = (s0 + total + 3u) >> 2;
-    for (uint32_t j = lane; j <= nw; j += kWave) L.heapw[j] = g[j];
+        // Rare path: re-read each hit word with its successors (L1/L2 hits),
+        // check 8-byte windows and queue verified starts.
+        for (;;) {
+            const bool have = hits != 0u;
+            if (__ballot(have) == 0) break;
+            uint32_t e0 = 0, e1 = 0, e2 = 0, q = 0;
+            if (have) {
+                const int j = __builtin_ctz(hits);
+                hits &= hits - 1;
+                const int it = j >> 2, wd = j & 3;
+                const uint32_t v = base + (uint32_t)it * kWave + (uint32_t)lane;
+                const uint4 x = g[v], y = g[v + 1];
+                const uint32_t f[6] = {x.x, x.y, x.z, x.w, y.x, y.y};
+                e0 = wd == 0 ? f[0] : wd == 1 ? f[1] : wd == 2 ? f[2] : f[3];
+                e1 = wd == 0 ? f[1] : wd == 1 ? f[2] : wd == 2 ? f[3] : f[4];
+                e2 = wd == 0 ? f[2] : wd == 1 ? f[3] : wd == 2 ? f[4] : f[5];
+                q = v * 16u + 4u * (uint32_t)wd;
+            }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        L.first1[64 * k + lane] = 0xFFFFFFFFu;
-        L.last2[64 * k + lane] = 0u;
-    }
-    wave_lds_sync();
-
-    const uint32_t a1 = rep4(p.s1[0]), a2 = rep4(p.s2[0]);
-    const uint32_t b1 = rep4(p.n1 > 1 ? p.s1[1] : 0), b2 = rep4(p.n2 > 1 ? p.s2[1] : 0);
-    const bool two1 = p.n1 > 1, two2 = p.n2 > 1;
-    const uint8_t* hb = reinterpret_cast<const uint8_t*>(L.heapw);
-    for (uint32_t j = lane; j < nw; j += kWave) {
-        uint32_t w = L.heapw[j], nx = L.heapw[j + 1];
-        uint32_t sh = __builtin_amdgcn_alignbit(nx, w, 8);  // bytes 1..4
-        uint32_t z1 = (w ^ a1) | (two1 ? (sh ^ b1) : 0u);
-        uint32_t z2 = (w ^ a2) | (two2 ? (sh ^ b2) : 0u);
-        uint32_t f1 = zero_byte_flags(z1), f2 = zero_byte_flags(z2);
-        if ((f1 | f2) == 0u) continue;
-        for (int t = 0; t < 4; ++t) {
-            uint32_t bit = 0x80u << (8 * t);
-            if (!((f1 | f2) & bit)) continue;
-            uint32_t q = 4 * j + t;
-            if (q < s0 || q - s0 >= total) continue;
-            uint32_t pos = q - s0;
-            int r = row_of(L.offs, pos);
-            uint32_t rend = L.offs[r + 1];
-            if ((f1 & bit) && pos + p.n1 <= rend && str_eq_lds(hb, q, p.s1, p.n1))
-                atomicMin(&L.first1[r], pos);
-            if ((f2 & bit) && pos + p.n2 <= rend && str_eq_lds(hb, q, p.s2, p.n2))
-                atomicMax(&L.last2[r], pos + 1);
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t lo = t ? __builtin_amdgcn_alignbit(e1, e0, 8 * t) : e0;
+                const uint32_t hi = t ? __builtin_amdgcn_alignbit(e2, e1, 8 * t) : e1;
+                const uint64_t win8 = (uint64_t)lo | ((uint64_t)hi << 32);
+                const uint32_t qt = q + t;
+                const bool inr = have && qt >= s0 && qt - s0 < total;
+                const bool v1 = inr && (win8 & P1.m8) == P1.p8;
+                const bool v2 = inr && (win8 & P2.m8) == P2.p8;
+                const bool emit = v1 || v2;
+                const uint64_t bal = __ballot(emit);
+                if (emit) L.cand[ncand + bits_below(bal)] = ((qt - s0) << 2) | (uint32_t)v1 | ((uint32_t)v2 << 1);
+                ncand += (int)__popcll(bal);
+                if (ncand > kCandCap - kWave) {
+                    resolve_hits(L, ncand, p, hs, lane);
+                    ncand = 0;
+                }
+            }
+        }
+        if (base + kSegIters * kWave >= nvec) break;
+        const uint32_t nb = base + kSegIters * kWave;
+#pragma unroll
+        for (int it = 0; it < kSegIters; ++it) {
+            uint32_t v = nb + it * kWave + lane;
+            W[it] = v <= nvec ? g[v] : make_uint4(0u, 0u, 0u, 0u);
         }
     }
+    if (ncand) resolve_hits(L, ncand, p, hs, lane);
     wave_lds_sync();
+    uint32_t res = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int i = 64 * k + lane;
@@ -327,25 +416,32 @@ __device__ uint32_t eval_str_pred(const DevCol& c, const DevPred& p, int m, int 
 }
 
 // ---------------------------------------------------------------------------
-// Value slots carried by a surviving row (uniform slot ids -> registers)
+// Value slots carried by a surviving row.  Fact-column loads occupy slots
+// 0..nloads-1, probe payloads the slots after them.  In the fused kernel the
+// slots live in the wave's LDS area (one int64 column per lane, so runtime
+// slot ids cost nothing); the fragmented kernels keep them in registers.
 // ---------------------------------------------------------------------------
-struct Slots {
-    int64_t v[kMaxSlots];
+struct LdsSlots {
+    int64_t* p;  // this lane's slot 0; slot s at p[s * kWave]
+    __device__ __forceinline__ void set(int id, int64_t x) const { p[id * kWave] = x; }
+    __device__ __forceinline__ int64_t get(int id) const { return p[id * kWave]; }
 };
 
-__device__ __forceinline__ void set_slot(Slots& s, int id, int64_t x) {
+struct RegSlots {
+    int64_t v[kMaxSlots];
+    __device__ __forceinline__ void set(int id, int64_t x) {
 #pragma unroll
-    for (int i = 0; i < kMaxSlots; ++i)
-        if (i == id) s.v[i] = x;
-}
-
-__device__ __forceinline__ int64_t get_slot(const Slots& s, int id) {
-    int64_t x = 0;
+        for (int i = 0; i < kMaxSlots; ++i)
+            if (i == id) v[i] = x;
+    }
+    __device__ __forceinline__ int64_t get(int id) const {
+        int64_t x = 0;
 #pragma unroll
-    for (int i = 0; i < kMaxSlots; ++i)
-        if (i == id) x = s.v[i];
-    return x;
-}
+        for (int i = 0; i < kMaxSlots; ++i)
+            if (i == id) x = v[i];
+        return x;
+    }
+};
 
 __device__ __forceinline__ uint32_t hash32(int32_t key, int log2cap) {
     return log2cap ? ((uint32_t)key * 0x9E3779B1u) >> (32 - log2cap) : 0u;
@@ -373,8 +469,7 @@ __device__ __forceinline__ int64_t hash_payload(const DevHash& h, const uint8_t*
     const uint8_t* base;
     if (kLds) {
         // payload arrays follow the keys at the same relative offsets
-        base = smem_shared + h.lds_off +
-               ((const uint8_t*)h.pay[k] - (const uint8_t*)h.keys);
+        base = smem_shared + h.lds_off + ((const uint8_t*)h.pay[k] - (const uint8_t*)h.keys);
     } else {
         base = (const uint8_t*)h.pay[k];
     }
@@ -385,79 +480,80 @@ __device__ __forceinline__ int64_t hash_payload(const DevHash& h, const uint8_t*
 // ---------------------------------------------------------------------------
 // Aggregation of one surviving row into the (LDS or global) group table
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool group_index(const DevQuery& Q, const Slots& sv, int64_t& g) {
+template <class S>
+__device__ __forceinline__ bool group_index(const DevQuery& Q, const S& sv, int64_t& g) {
     g = 0;
     for (int k = 0; k < Q.nkeys; ++k) {
         const DevKey& K = Q.keys[k];
-        int64_t d = get_slot(sv, K.slot) - K.min;
+        int64_t d = sv.get(K.slot) - K.min;
         if (d < 0 || d >= K.card) return false;
         g += d * K.stride;
     }
     return true;
 }
 
-__device__ __forceinline__ int64_t acc_value(const DevAcc& A, const Slots& sv) {
+template <class S>
+__device__ __forceinline__ int64_t acc_value(const DevAcc& A, const S& sv) {
     int64_t prod = 1;
     for (int t = 0; t < A.nterms; ++t) {
         const DevTerm& T = A.t[t];
-        int64_t x = T.slot >= 0 ? T.mul * get_slot(sv, T.slot) + T.add : T.add;
+        int64_t x = T.slot >= 0 ? T.mul * sv.get(T.slot) + T.add : T.add;
         prod *= x;
     }
     return prod;
 }
 
-__device__ __forceinline__ void aggregate_row(const DevQuery& Q, uint8_t* smem_shared, const Slots& sv,
+template <class S>
+__device__ __forceinline__ void aggregate_row(const DevQuery& Q, uint8_t* smem_shared, const S& sv,
                                               int64_t g) {
     const int nacc = Q.nacc;
-    if (Q.agg_lds) {
-        unsigned long long* T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc;
-        atomicAdd(&T[0], 1ull);
-        for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
-    } else {
-        unsigned long long* T = reinterpret_cast<unsigned long long*>(Q.agg) + g * nacc;
-        atomicAdd(&T[0], 1ull);
-        for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
-    }
+    unsigned long long* T = Q.agg_lds
+        ? reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc
+        : reinterpret_cast<unsigned long long*>(Q.agg) + g * nacc;
+    atomicAdd(&T[0], 1ull);
+    for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
 }
 
 // ---------------------------------------------------------------------------
-// Stage B: probes, value loads and aggregation for one row (lane-local)
+// Stage B: probes, value loads and aggregation of one row per lane.  m and i
+// may differ between lanes (rows queued from several mini blocks).
 // ---------------------------------------------------------------------------
-template <bool kLdsAny>
-__device__ __forceinline__ void process_row(const DevQuery& Q, uint8_t* smem_shared, int m, int i,
-                                            bool active, bool& ok_hdr) {
+__device__ __forceinline__ void stage_b(const DevQuery& Q, uint8_t* smem_shared, LdsSlots sv, int m, int i,
+                                        bool active, bool& ok_hdr) {
     bool ok = active;
-    Slots sv;
-#pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) sv.v[s] = 0;
     const int nprobes = Q.nprobes;
     for (int j = 0; j < nprobes; ++j) {
         if (__ballot(ok) == 0) return;
         const DevProbe& P = Q.probes[j];
         if (ok) {
-            int64_t fk = decode_at(Q.cols[P.fk_col], m, i, ok_hdr);
             const DevCol& fc = Q.cols[P.fk_col];
+            int64_t fk = decode_at(fc, m, i, ok_hdr);
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, ok_hdr);
-            int slot = (kLdsAny && P.h.lds_off >= 0) ? hash_find<true>(P.h, smem_shared, fk)
-                                                     : hash_find<false>(P.h, smem_shared, fk);
+            const bool lds = P.h.lds_off >= 0;
+            int slot = lds ? hash_find<true>(P.h, smem_shared, fk) : hash_find<false>(P.h, smem_shared, fk);
             ok = slot >= 0;
             if (ok) {
                 for (int k = 0; k < P.h.npay; ++k) {
                     if (P.pay_slot[k] < 0) continue;
-                    int64_t pv = (kLdsAny && P.h.lds_off >= 0) ? hash_payload<true>(P.h, smem_shared, k, slot)
-                                                               : hash_payload<false>(P.h, smem_shared, k, slot);
-                    set_slot(sv, P.pay_slot[k], pv);
+                    int64_t pv = lds ? hash_payload<true>(P.h, smem_shared, k, slot)
+                                     : hash_payload<false>(P.h, smem_shared, k, slot);
+                    sv.set(P.pay_slot[k], pv);
                 }
             }
         }
     }
     if (!ok) return;
-    for (int l = 0; l < Q.nloads; ++l) {
-        const DevLoad& Ld = Q.loads[l];
-        const DevCol& lc = Q.cols[Ld.col];
-        int64_t x = decode_at(lc, m, i, ok_hdr);
-        if (Ld.dict_val) x = dict_value(lc, x, ok_hdr);
-        set_slot(sv, Ld.slot, x);
+    // Fact values for slots 0..nloads-1.
+    const int nloads = Q.nloads;
+#pragma unroll
+    for (int s = 0; s < kMaxSlots; ++s) {
+        if (s < nloads) {
+            const DevLoad& Ld = Q.loads[s];
+            const DevCol& c = Q.cols[Ld.col];
+            int64_t x = decode_at(c, m, i, ok_hdr);
+            if (Ld.dict_val) x = dict_value(c, x, ok_hdr);
+            sv.set(s, x);
+        }
     }
     int64_t g;
     if (!group_index(Q, sv, g)) { ok_hdr = false; return; }
@@ -465,22 +561,42 @@ __device__ __forceinline__ void process_row(const DevQuery& Q, uint8_t* smem_sha
 }
 
 // ---------------------------------------------------------------------------
-// One mini block of one plan, by one wave
+// One mini block of one plan, by one wave (stage A), survivors queued
 // ---------------------------------------------------------------------------
-template <bool kLdsAny>
-__device__ void process_tile(const DevQuery& Q, uint8_t* smem_shared, uint8_t* wave_area, bool str_stage,
-                             int m, int lane, bool& ok_hdr) {
+struct WaveArea {
+    uint32_t* pend;    // [kPendCap] queued surviving row ids
+    int64_t* slots;    // [kMaxSlots][kWave] stage-B values
+    uint32_t* offs;    // [260] string row offsets
+    uint32_t* first1;  // [256] leftmost s1 start per row
+    uint32_t* last2;   // [256] rightmost s2 start + 1 per row
+    uint32_t* cand;    // [kCandCap] string-predicate hits awaiting their row
+};
+
+__device__ __forceinline__ void flush_pending(const DevQuery& Q, uint8_t* smem_shared, const WaveArea& W, int& npend, int lane,
+                              bool& ok_hdr) {
+    wave_lds_sync();
+    for (int base = 0; base < npend; base += kWave) {
+        int idx = base + lane;
+        bool act = idx < npend;
+        uint32_t row = W.pend[act ? idx : 0];
+        stage_b(Q, smem_shared, LdsSlots{W.slots + lane}, (int)(row >> 8), (int)(row & 255u), act, ok_hdr);
+    }
+    npend = 0;
+    wave_lds_sync();
+}
+
+__device__ __forceinline__ void process_tile(const DevQuery& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
+                             int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
     const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
-    uint16_t* rows = reinterpret_cast<uint16_t*>(wave_area);
     const int npreds = Q.npreds;
 
     if (npreds == 0) {
-        // No fact predicate: every valid row goes to the probe/aggregate stage.
+        // No fact predicate: every valid row goes straight to stage B.
         for (int k = 0; k < 4; ++k) {
-            int i = 64 * k + lane;
             if (64 * k >= nvalid) break;
-            process_row<kLdsAny>(Q, smem_shared, m, i, i < nvalid, ok_hdr);
+            int i = 64 * k + lane;
+            stage_b(Q, smem_shared, LdsSlots{W.slots + lane}, m, i, i < nvalid, ok_hdr);
         }
         return;
     }
@@ -494,13 +610,9 @@ __device__ void process_tile(const DevQuery& Q, uint8_t* smem_shared, uint8_t* w
     for (int a = 0; a < npreds; ++a) {
         const DevPred& P = Q.preds[a];
         if (P.kind == PK_STR) {
-            if (!str_stage) { ok_hdr = false; return; }
-            StrLds L;
-            L.offs = reinterpret_cast<uint32_t*>(wave_area + 512);
-            L.first1 = L.offs + 260;
-            L.last2 = L.first1 + 256;
-            L.heapw = L.last2 + 256;
-            mask &= eval_str_pred(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            const StrLds L{W.offs, W.first1, W.last2, W.cand};
+            if (P.n1 >= 4 && P.n2 >= 4) mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            else mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
         } else {
             if (P.col != last_col) {
                 ok_hdr &= decode_dense(Q.cols[P.col], m, lane, v);
@@ -511,27 +623,32 @@ __device__ void process_tile(const DevQuery& Q, uint8_t* smem_shared, uint8_t* w
         if (__ballot(mask != 0) == 0) return;  // no survivor in this mini block
     }
 
-    // Compact survivors (wave ballot + mbcnt) into the wave's row list.
-    uint32_t nsurv = 0;
+    // Queue survivors (wave ballot + mbcnt compaction).
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         bool bit = (mask >> k) & 1u;
         uint64_t b = __ballot(bit);
-        if (bit) rows[nsurv + bits_below(b)] = (uint16_t)(64 * k + lane);
-        nsurv += (uint32_t)__popcll(b);
+        if (bit) W.pend[npend + bits_below(b)] = (uint32_t)(row0 + 64 * k + lane);
+        npend += (int)__popcll(b);
     }
-    wave_lds_sync();
-    for (uint32_t base = 0; base < nsurv; base += kWave) {
-        uint32_t idx = base + lane;
-        bool act = idx < nsurv;
-        int i = act ? rows[idx] : 0;
-        process_row<kLdsAny>(Q, smem_shared, m, i, act, ok_hdr);
-    }
-    wave_lds_sync();
+    if (npend >= kWave) flush_pending(Q, smem_shared, W, npend, lane, ok_hdr);
 }
 
-__device__ __forceinline__ size_t wave_area_bytes(bool str_stage) {
-    return 512 + (str_stage ? (1040 + 1024 + 1024 + kStrHeapCap + 64) : 0);
+// Per-wave LDS: stage-B slots, then (plans with fact predicates) the
+// survivor queue, then (string predicates) row offsets, s1 and s2 starts.
+__host__ __device__ constexpr size_t wave_area_bytes(bool str_stage, bool pend_stage) {
+    return kMaxSlots * kWave * 8 + (pend_stage ? kPendCap * 4 : 0) + (str_stage ? (260 * 4 + 2 * 256 * 4 + kCandCap * 4) : 0);
+}
+
+__device__ __forceinline__ WaveArea wave_area(uint8_t* p, bool pend_stage) {
+    WaveArea W;
+    W.slots = reinterpret_cast<int64_t*>(p);
+    W.pend = reinterpret_cast<uint32_t*>(p + kMaxSlots * kWave * 8);
+    W.offs = W.pend + (pend_stage ? kPendCap : 0);
+    W.first1 = W.offs + 260;
+    W.last2 = W.first1 + 256;
+    W.cand = W.last2 + 256;
+    return W;
 }
 
 // Merge the workgroup's LDS group table into the plan's global table.
@@ -599,20 +716,24 @@ __device__ void emit_records(const DevQuery& Q, int32_t* ctrl) {
 }
 
 // ---------------------------------------------------------------------------
-// The persistent fused kernel
+// The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void fused_kernel(BatchArgs a) {
+template <int NW>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
     uint8_t* shared_area = smem + 64;
     const bool str_stage = a.str_stage != 0;
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
-    uint8_t* wave_area = smem + 64 + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage);
+    const bool pend_stage = a.pend_stage != 0;
+    const WaveArea W =
+        wave_area(smem + 64 + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage, pend_stage), pend_stage);
     const int total_items = a.item_start[a.nq];
 
     int cur = -1;
     bool ok_hdr = true;
+    int npend = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(&a.counters[0], 1u);
@@ -637,11 +758,8 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(BatchArgs a) {
         }
         const int mb0 = (item - a.item_start[qi]) * a.mb_per_item;
         const int mb1 = min(mb0 + a.mb_per_item, Q.nmb);
-        const bool lds_any = Q.lds_shared > 0;
-        for (int m = mb0 + wave; m < mb1; m += kWaves) {
-            if (lds_any) process_tile<true>(Q, shared_area, wave_area, str_stage, m, lane, ok_hdr);
-            else process_tile<false>(Q, shared_area, wave_area, str_stage, m, lane, ok_hdr);
-        }
+        for (int m = mb0 + wave; m < mb1; m += NW) process_tile(Q, shared_area, W, m, lane, npend, ok_hdr);
+        if (npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
         __syncthreads();
@@ -697,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs*
     const int nw = (gridDim.x * blockDim.x) >> 6;
     bool ok = true;
     unsigned long long cnt = 0;
-    long long mn[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, mx[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    long long mn0 = INT64_MAX, mx0 = INT64_MIN, mn1 = INT64_MAX, mx1 = INT64_MIN, mn2 = INT64_MAX, mx2 = INT64_MIN;
     for (int m = gw; m < A.nmb; m += nw) {
         const int nvalid = (int)min((int64_t)kMB, A.nrows - (int64_t)m * kMB);
         int64_t key[4], pay[2][4];
@@ -705,20 +823,18 @@ __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs*
         for (int k = 0; k < 4; ++k) {
             if (!((mask >> k) & 1u)) continue;
             cnt += 1;
-            mn[0] = min(mn[0], (long long)key[k]);
-            mx[0] = max(mx[0], (long long)key[k]);
-            for (int j = 0; j < A.npay; ++j) {
-                mn[1 + j] = min(mn[1 + j], (long long)pay[j][k]);
-                mx[1 + j] = max(mx[1 + j], (long long)pay[j][k]);
-            }
+            mn0 = min(mn0, (long long)key[k]);
+            mx0 = max(mx0, (long long)key[k]);
+            if (A.npay > 0) { mn1 = min(mn1, (long long)pay[0][k]); mx1 = max(mx1, (long long)pay[0][k]); }
+            if (A.npay > 1) { mn2 = min(mn2, (long long)pay[1][k]); mx2 = max(mx2, (long long)pay[1][k]); }
         }
     }
     if (cnt) {
         atomicAdd(A.count, cnt);
-        for (int j = 0; j < 1 + A.npay; ++j) {
-            atomicMin(&A.mm[2 * j], mn[j]);
-            atomicMax(&A.mm[2 * j + 1], mx[j]);
-        }
+        atomicMin(&A.mm[0], mn0);
+        atomicMax(&A.mm[1], mx0);
+        if (A.npay > 0) { atomicMin(&A.mm[2], mn1); atomicMax(&A.mm[3], mx1); }
+        if (A.npay > 1) { atomicMin(&A.mm[4], mn2); atomicMax(&A.mm[5], mx2); }
     }
     if (!ok) atomicOr(A.status, ST_CORRUPT);
 }
@@ -768,7 +884,9 @@ __global__ void fill_kernel(T* p, T v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Fragmented execution: one kernel per step, intermediates in HBM
+// Fragmented execution: one kernel per step, intermediates in HBM.  Each
+// kernel is the straightforward data-parallel form of its step, with
+// workgroup-level aggregation of its atomics.
 // ---------------------------------------------------------------------------
 // Decode one integer column to int64 (codes for DICT).
 __global__ __launch_bounds__(kBlock) void frag_decode_int(const DevQuery* __restrict__ q, int c, int64_t* out) {
@@ -813,7 +931,16 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
             carry += readlane_u64(s, 63);
         }
         if (carry != h1) ok = false;
-        for (uint64_t b = h0 + lane; b < h1; b += kWave) bytes[b] = C.heap[b];
+        // copy the bytes: 16-byte pieces where both sides are aligned
+        uint64_t b = h0;
+        while (b < h1 && (b & 15)) {
+            if (b + lane < h1 && ((b + lane) & ~uint64_t(15)) == (b & ~uint64_t(15))) bytes[b + lane] = C.heap[b + lane];
+            b = (b | 15) + 1;
+        }
+        for (uint64_t v = b + 16 * (uint64_t)lane; v + 16 <= h1; v += 16 * kWave)
+            *reinterpret_cast<uint4*>(bytes + v) = *reinterpret_cast<const uint4*>(C.heap + v);
+        uint64_t tail = b + ((h1 > b ? h1 - b : 0) & ~uint64_t(15));
+        if (tail + lane < h1) bytes[tail + lane] = C.heap[tail + lane];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) off[Q.nrows] = (int64_t)Q.cols[c].heap_bytes;
     if (!ok) atomicOr(Q.status, ST_CORRUPT);
@@ -843,20 +970,38 @@ __global__ void frag_filter_str(const DevQuery* __restrict__ q, int pi, const in
     }
 }
 
-// flags -> row list (order not preserved; aggregation is order-free)
+// flags -> row list (order not preserved; aggregation is order-free).  One
+// global atomic per workgroup step of 1024 rows.
 __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restrict__ q, const uint8_t* flags,
                                                        int32_t* rows, unsigned long long* count) {
+    __shared__ uint32_t wcnt[kWaves + 1];
+    __shared__ unsigned long long base_s;
     const DevQuery& Q = *q;
-    const int lane = lane_id();
-    for (int64_t b0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~63ll; b0 < Q.nrows;
-         b0 += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = b0 + lane;
-        bool f = r < Q.nrows && flags[r];
-        uint64_t bal = __ballot(f);
-        unsigned long long base = 0;
-        if (lane == 0 && bal) base = atomicAdd(count, (unsigned long long)__popcll(bal));
-        base = __shfl(base, 0, kWave);
-        if (f) rows[base + bits_below(bal)] = (int32_t)r;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int64_t b0 = (int64_t)blockIdx.x * 1024; b0 < Q.nrows; b0 += (int64_t)gridDim.x * 1024) {
+        bool f[4];
+        uint32_t c = 0;
+        uint64_t bal[4];
+        for (int k = 0; k < 4; ++k) {
+            int64_t r = b0 + wave * 256 + 64 * k + lane;
+            f[k] = r < Q.nrows && flags[r];
+            bal[k] = __ballot(f[k]);
+            c += (uint32_t)__popcll(bal[k]);
+        }
+        if (lane == 0) wcnt[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kWaves; ++w) { uint32_t x = wcnt[w]; wcnt[w] = t; t += x; }
+            base_s = t ? atomicAdd(count, (unsigned long long)t) : 0;
+        }
+        __syncthreads();
+        unsigned long long o = base_s + wcnt[wave];
+        for (int k = 0; k < 4; ++k) {
+            if (f[k]) rows[o + bits_below(bal[k])] = (int32_t)(b0 + wave * 256 + 64 * k + lane);
+            o += (uint32_t)__popcll(bal[k]);
+        }
+        __syncthreads();
     }
 }
 
@@ -908,22 +1053,28 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
 }
 
 // Aggregate the final row list: fact values gathered from the decoded
-// columns, payloads from the aligned arrays.
+// columns, payloads from the aligned arrays; small group tables are
+// accumulated per workgroup in LDS first.
 __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restrict__ q, const int32_t* rows,
                                                          const unsigned long long* nrows_list, const FragBuffers fb,
                                                          int src) {
+    __shared__ unsigned long long tab[4096];
     const DevQuery& Q = *q;
     const int64_t n = (int64_t)*nrows_list;
+    const bool local = Q.ngroups * Q.nacc <= 4096;
+    if (local)
+        for (int e = threadIdx.x; e < Q.ngroups * Q.nacc; e += blockDim.x) tab[e] = 0;
+    __syncthreads();
     bool okall = true;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         int32_t r = rows[e];
-        Slots sv;
+        RegSlots sv;
         for (int s = 0; s < kMaxSlots; ++s) sv.v[s] = 0;
         int pidx = 0;
         for (int j = 0; j < Q.nprobes; ++j) {
             for (int k = 0; k < Q.probes[j].h.npay; ++k) {
                 int sl = Q.probes[j].pay_slot[k];
-                if (sl >= 0) set_slot(sv, sl, fb.pay[src][pidx][e]);
+                if (sl >= 0) sv.set(sl, fb.pay[src][pidx][e]);
                 ++pidx;
             }
         }
@@ -931,14 +1082,18 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
             const DevLoad& Ld = Q.loads[l];
             int64_t x = fb.dec[Ld.col][r];
             if (Ld.dict_val) x = dict_value(Q.cols[Ld.col], x, okall);
-            set_slot(sv, Ld.slot, x);
+            sv.set(l, x);
         }
         int64_t g;
         if (!group_index(Q, sv, g)) { okall = false; continue; }
-        unsigned long long* T = reinterpret_cast<unsigned long long*>(Q.agg) + g * Q.nacc;
+        unsigned long long* T = local ? &tab[g * Q.nacc] : reinterpret_cast<unsigned long long*>(Q.agg) + g * Q.nacc;
         atomicAdd(&T[0], 1ull);
         for (int a = 1; a < Q.nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
     }
+    __syncthreads();
+    if (local)
+        for (int e = threadIdx.x; e < Q.ngroups * Q.nacc; e += blockDim.x)
+            if (tab[e]) atomicAdd(reinterpret_cast<unsigned long long*>(Q.agg) + e, tab[e]);
     if (!okall) atomicOr(Q.status, ST_CORRUPT);
 }
 
@@ -953,17 +1108,29 @@ __global__ void frag_reset_counts(unsigned long long* c, int n) {
     if (threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-}  // namespace
-
-hipError_t launch_fused(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
+template <int NW>
+hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL(fused_kernel<NW>, dim3(grid), dim3(NW * kWave), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+}  // namespace
+
+size_t fused_wave_area_bytes(bool str, bool pend) { return wave_area_bytes(str, pend); }
+
+hipError_t launch_fused(const BatchArgs& a, int waves, int grid, size_t lds_bytes, hipStream_t s) {
+    switch (waves) {
+        case 4: return launch_fused_nw<4>(a, grid, lds_bytes, s);
+        case 8: return launch_fused_nw<8>(a, grid, lds_bytes, s);
+        case 16: return launch_fused_nw<16>(a, grid, lds_bytes, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_hash_count(const HashBuildArgs* d_args, int grid, hipStream_t s) {

@@ -661,7 +661,7 @@ namespace {
 constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
-size_t wave_area_bytes(bool str) { return 512 + (str ? (1040 + 1024 + 1024 + kStrHeapCap + 64) : 0); }
+constexpr int kTargetWavesPerCU = 20;  // resident waves per CU the default launch aims for
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
 // shared area within budget; fills lds offsets and lds_shared.
@@ -727,7 +727,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         if (c->placement == DPF_PLACE_HOST) return fail(DPF_ERR_INVALID_ARG, "fact column not on the device");
         if (c->ctx != ctx) return fail(DPF_ERR_INVALID_ARG, "column from another context");
     }
-    if (nrows > (int64_t)INT32_MAX * kMB) return fail(DPF_ERR_UNSUPPORTED, "table too long");
+    if (nrows > (int64_t)UINT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "tables are limited to 2^32 - 1 rows");
 
     dpf_plan p = new (std::nothrow) dpf_plan_s();
     if (!p) return fail(DPF_ERR_OOM, "plan");
@@ -882,18 +882,28 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         if (ag.op == DPF_AGG_AVG) p->outcols.push_back({0, 0});
         q.nacc++;
     }
-    // slot loads and payload destinations
+    // Renumber slots so fact-column loads take slots 0..nloads-1 (the kernel
+    // writes those with compile-time indices) and payloads the ones after.
+    std::vector<int> remap(slots.size());
     q.nloads = 0;
     for (size_t s = 0; s < slots.size(); ++s) {
-        if (slots[s].kind == 0) {
-            q.loads[q.nloads].col = slots[s].a;
-            q.loads[q.nloads].slot = (int32_t)s;
-            q.loads[q.nloads].dict_val = desc->cols[slots[s].a]->host.enc == DPF_ENC_DICT && slots[s].b == 1;
-            q.nloads++;
-        } else {
-            q.probes[slots[s].a].pay_slot[slots[s].b] = (int32_t)s;
-        }
+        if (slots[s].kind != 0) continue;
+        remap[s] = q.nloads;
+        q.loads[q.nloads].col = slots[s].a;
+        q.loads[q.nloads].slot = q.nloads;
+        q.loads[q.nloads].dict_val = desc->cols[slots[s].a]->host.enc == DPF_ENC_DICT && slots[s].b == 1;
+        q.nloads++;
     }
+    int next = q.nloads;
+    for (size_t s = 0; s < slots.size(); ++s) {
+        if (slots[s].kind == 0) continue;
+        remap[s] = next;
+        q.probes[slots[s].a].pay_slot[slots[s].b] = next++;
+    }
+    for (int k = 0; k < q.nkeys; ++k) q.keys[k].slot = remap[q.keys[k].slot];
+    for (int a = 1; a < q.nacc; ++a)
+        for (int t = 0; t < q.accs[a].nterms; ++t)
+            if (q.accs[a].t[t].slot >= 0) q.accs[a].t[t].slot = remap[q.accs[a].t[t].slot];
     assign_lds(p, -1);
 
     // device memory: [DevQuery][agg table][status][counters]
@@ -1022,7 +1032,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         }
     } else if (o.mode == DPF_MODE_FUSED) {
         if (n > kMaxBatch) return fail(DPF_ERR_UNSUPPORTED, "at most 64 plans per fused launch");
-        int rows_per_item = o.rows_per_item ? o.rows_per_item : 65536;
+        int rows_per_item = o.rows_per_item ? o.rows_per_item : 16384;
         if (rows_per_item < kMB || rows_per_item % kMB) return fail(DPF_ERR_INVALID_ARG, "rows_per_item: multiple of 256");
         // LDS placement follows the requested budget (re-uploads the
         // descriptor only when the budget changes)
@@ -1040,7 +1050,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         a.mb_per_item = rows_per_item / kMB;
         a.counters = plans[0]->counters;
         int32_t items = 0;
-        bool str = false;
+        bool str = false, pend = false;
         int32_t shared = 0;
         for (int i = 0; i < n; ++i) {
             const DevQuery& q = plans[i]->hq;
@@ -1048,20 +1058,33 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
             a.item_start[i] = items;
             items += (q.nmb + a.mb_per_item - 1) / a.mb_per_item;
             str |= q.has_str != 0;
+            pend |= q.npreds > 0;
             shared = std::max(shared, q.lds_shared);
         }
         a.item_start[n] = items;
         a.lds_shared = (int32_t)align_up((size_t)shared, 16);
         a.str_stage = str;
-        const size_t lds = 64 + (size_t)a.lds_shared + kWaves * wave_area_bytes(str);
+        a.pend_stage = pend;
+        auto lds_for = [&](int w) { return 64 + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
+        // Waves per workgroup: large LDS-resident dimension tables are shared
+        // by more waves (one copy per workgroup); otherwise small workgroups.
+        int waves = o.waves_per_wg;
+        if (waves == 0) {
+            waves = 4;
+            if (a.lds_shared >= 32 * 1024)
+                for (int w : {16, 8})
+                    if ((int64_t)lds_for(w) <= ctx->lds_per_block) { waves = w; break; }
+        }
+        if (waves != 4 && waves != 8 && waves != 16) return fail(DPF_ERR_INVALID_ARG, "waves_per_wg: 4, 8 or 16");
+        const size_t lds = lds_for(waves);
         if ((int64_t)lds > ctx->lds_per_block)
             return fail(DPF_ERR_UNSUPPORTED, "plan LDS needs exceed the workgroup limit; lower lds_hash_bytes");
-        int wg = o.wg_per_cu;
-        if (wg <= 0) wg = 4;
         const int lds_cu = 160 * 1024;
+        int wg = o.wg_per_cu;
+        if (wg <= 0) wg = std::max(1, kTargetWavesPerCU / waves);
         wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
         const int grid = std::max(1, ctx->ncu * wg);
-        HIP_TRY(launch_fused(a, grid, lds, s));
+        HIP_TRY(launch_fused(a, waves, grid, lds, s));
         ctx->launches++;
     } else {
         return fail(DPF_ERR_INVALID_ARG, "unknown execution mode");
