@@ -25,9 +25,33 @@
 namespace dpf {
 namespace {
 
+// Descriptors and encoded columns are read-only during a launch, so the
+// kernels read them through the constant address space: wave-uniform reads
+// (headers, descriptor fields) become scalar loads and per-lane reads become
+// global loads, never flat ones.
+#define DPF_AS_CONST __attribute__((address_space(4)))
+template <class T>
+using cptr = const DPF_AS_CONST T*;
+template <class T>
+__device__ __forceinline__ cptr<T> ro(const T* p) { return (cptr<T>)p; }
+using CQ = const DPF_AS_CONST DevQuery;
+using CC = const DPF_AS_CONST DevCol;
+using CP = const DPF_AS_CONST DevPred;
+using CH = const DPF_AS_CONST DevHash;
+using CPR = const DPF_AS_CONST DevProbe;
+using CL = const DPF_AS_CONST DevLoad;
+using CK = const DPF_AS_CONST DevKey;
+using CT = const DPF_AS_CONST DevTerm;
+using CA = const DPF_AS_CONST DevAcc;
+using CHB = const DPF_AS_CONST HashBuildArgs;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld4(cptr<uint4> g, uint32_t i) {
+    const u32x4 t = ((cptr<u32x4>)g)[i];
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+
 constexpr int kPendCap = 320;   // per-wave survivor queue (64 pending + one mini block)
 constexpr int kSegIters = 8;    // 16-byte string loads per lane per segment (8 KB per wave)
-constexpr int kCandCap = 256;   // per-wave queue of verified string-predicate hits
 
 // ---------------------------------------------------------------------------
 // Wave helpers
@@ -46,21 +70,44 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint64_t y = __shfl_up(x, (unsigned)d, kWave);
-        if (lane >= d) x += y;
-    }
+// Cross-lane moves through DPP (GFX9 data-parallel primitives): no address
+// registers, no LDS.  A lane whose source is outside the pattern, or whose
+// row is masked off, receives 0.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, kRowMask, 0xf, false);
+}
+
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    const uint32_t lo = dpp_u32<kCtrl, kRowMask>((uint32_t)x);
+    const uint32_t hi = dpp_u32<kCtrl, kRowMask>((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive wave scans: shifts 1, 2, 4, 8 inside each 16-lane row, then lane
+// 15 of a row is added to the next row and lane 31 to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += dpp_u32<kDppRowShr1>(x);
+    x += dpp_u32<kDppRowShr2>(x);
+    x += dpp_u32<kDppRowShr4>(x);
+    x += dpp_u32<kDppRowShr8>(x);
+    x += dpp_u32<kDppRowBcast15, 0xa>(x);
+    x += dpp_u32<kDppRowBcast31, 0xc>(x);
     return x;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t y = __shfl_up(x, (unsigned)d, kWave);
-        if (lane >= d) x += y;
-    }
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    x += dpp_u64<kDppRowShr1>(x);
+    x += dpp_u64<kDppRowShr2>(x);
+    x += dpp_u64<kDppRowShr4>(x);
+    x += dpp_u64<kDppRowShr8>(x);
+    x += dpp_u64<kDppRowBcast15, 0xa>(x);
+    x += dpp_u64<kDppRowBcast31, 0xc>(x);
     return x;
 }
 
@@ -77,10 +124,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 typedef uint64_t u64_a4 __attribute__((aligned(4)));
 
-__device__ __forceinline__ uint64_t bits_at(const uint32_t* w, uint32_t bitpos, int b) {
-    const uint32_t* p = w + (bitpos >> 5);
+__device__ __forceinline__ uint64_t bits_at(cptr<uint32_t> w, uint32_t bitpos, int b) {
+    cptr<uint32_t> p = w + (bitpos >> 5);
     uint32_t sh = bitpos & 31u;
-    uint64_t x = *reinterpret_cast<const u64_a4*>(p) >> sh;
+    uint64_t x = *(cptr<u64_a4>)p >> sh;
     if (b > 32) {
         uint64_t hi = p[2];
         if (sh) x |= hi << (64 - sh);
@@ -90,21 +137,21 @@ __device__ __forceinline__ uint64_t bits_at(const uint32_t* w, uint32_t bitpos, 
 
 struct MbHdr {
     int64_t base;
-    const uint32_t* w;
+    cptr<uint32_t> w;
     int b;
     bool ok;
 };
 
 // Mini-block header with consistency checks (a corrupt header must not
 // steer a load out of bounds).
-__device__ __forceinline__ MbHdr mb_hdr(const DevCol& c, int m) {
+__device__ __forceinline__ MbHdr mb_hdr(CC& c, int m) {
     MbHdr h;
-    uint32_t w0 = c.woff[m], w1 = c.woff[m + 1];
+    uint32_t w0 = ro(c.woff)[m], w1 = ro(c.woff)[m + 1];
     uint32_t nw = w1 - w0;
     h.ok = (w0 <= w1) && (w1 <= c.nwords) && ((nw & 7u) == 0) && (nw <= 512u);
     h.b = (int)(nw >> 3);
-    h.base = c.base[m];
-    h.w = c.words + (h.ok ? w0 : 0);
+    h.base = ro(c.base)[m];
+    h.w = ro(c.words) + (h.ok ? w0 : 0);
     if (!h.ok) h.b = 0;
     return h;
 }
@@ -112,7 +159,7 @@ __device__ __forceinline__ MbHdr mb_hdr(const DevCol& c, int m) {
 // Dense decode of the wave's four rows (64k + lane) of mini block m.
 // DICT columns yield codes; VARLEN yields lengths.  Returns false on a
 // corrupt header.
-__device__ __forceinline__ bool decode_dense(const DevCol& c, int m, int lane, int64_t v[4]) {
+__device__ __forceinline__ bool decode_dense(CC& c, int m, int lane, int64_t v[4]) {
     MbHdr h = mb_hdr(c, m);
     uint64_t u[4];
     if (h.b == 0) {
@@ -124,11 +171,11 @@ __device__ __forceinline__ bool decode_dense(const DevCol& c, int m, int lane, i
     }
     if (c.enc == ENC_DELTA) {
         // value_i = anchor + i * dmin + sum_{j <= i} packed_j  (packed_0 = 0)
-        uint64_t dmin = (uint64_t)c.dmin[m];
+        uint64_t dmin = (uint64_t)ro(c.dmin)[m];
         uint64_t carry = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            uint64_t s = h.b ? wave_incl_scan_u64(u[k], lane) : 0;
+            uint64_t s = h.b ? wave_incl_scan_u64(u[k]) : 0;
             uint32_t i = 64 * k + lane;
             v[k] = (int64_t)((uint64_t)h.base + (uint64_t)i * dmin + carry + s);
             if (h.b) carry += readlane_u64(s, 63);
@@ -142,29 +189,29 @@ __device__ __forceinline__ bool decode_dense(const DevCol& c, int m, int lane, i
 
 // Value of row i of mini block m (random access).  DELTA sums the packed
 // differences up to i.
-__device__ __forceinline__ int64_t decode_at(const DevCol& c, int m, int i, bool& ok) {
+__device__ __forceinline__ int64_t decode_at(CC& c, int m, int i, bool& ok) {
     MbHdr h = mb_hdr(c, m);
     ok = ok && h.ok;
     if (c.enc == ENC_DELTA) {
         uint64_t s = 0;
         if (h.b)
             for (int j = 1; j <= i; ++j) s += bits_at(h.w, (uint32_t)j * (uint32_t)h.b, h.b);
-        return (int64_t)((uint64_t)h.base + (uint64_t)i * (uint64_t)c.dmin[m] + s);
+        return (int64_t)((uint64_t)h.base + (uint64_t)i * (uint64_t)ro(c.dmin)[m] + s);
     }
     uint64_t u = h.b ? bits_at(h.w, (uint32_t)i * (uint32_t)h.b, h.b) : 0;
     return (int64_t)((uint64_t)h.base + u);
 }
 
 // DICT code -> value (bounds-checked).
-__device__ __forceinline__ int64_t dict_value(const DevCol& c, int64_t code, bool& ok) {
+__device__ __forceinline__ int64_t dict_value(CC& c, int64_t code, bool& ok) {
     if (code < 0 || code >= c.ndict) { ok = false; return 0; }
-    return c.dict[code];
+    return ro(c.dict)[code];
 }
 
 // ---------------------------------------------------------------------------
 // Integer predicates on four dense values -> 4-bit mask
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t eval_int_pred(const DevPred& p, const int64_t* in_vals,
+__device__ __forceinline__ uint32_t eval_int_pred(CP& p, cptr<int64_t> in_vals,
                                                   const int64_t v[4]) {
     uint32_t mk = 0;
     const int kind = p.kind;
@@ -214,21 +261,23 @@ __device__ __forceinline__ int row_of(const uint32_t* offs, uint32_t p) {
     return lo;
 }
 
-__device__ __forceinline__ bool bytes_eq(const uint8_t* s, const uint8_t* w, int from, int n) {
+template <class S, class Wp>
+__device__ __forceinline__ bool bytes_eq(S s, Wp w, int from, int n) {
     for (int i = from; i < n; ++i)
         if (s[i] != w[i]) return false;
     return true;
 }
 
 // Does s[from, n) contain w (length nw)?
-__device__ bool contains_from(const uint8_t* s, uint32_t from, uint32_t n, const uint8_t* w, int nw) {
+template <class S, class Wp>
+__device__ bool contains_from(S s, uint32_t from, uint32_t n, Wp w, int nw) {
     for (uint32_t q = from; q + (uint32_t)nw <= n; ++q)
         if (s[q] == w[0] && bytes_eq(s + q, w, 1, nw)) return true;
     return false;
 }
 
 // LIKE '%s1%s2%' on one string where it rests (fragmented path).
-__device__ bool contains_seq_global(const uint8_t* s, uint32_t n, const DevPred& p) {
+__device__ bool contains_seq_global(const uint8_t* s, uint32_t n, CP& p) {
     for (uint32_t a = 0; a + (uint32_t)p.n1 <= n; ++a) {
         if (s[a] != p.s1[0] || !bytes_eq(s + a, p.s1, 1, p.n1)) continue;
         return contains_from(s, a + p.n1, n, p.s2, p.n2);  // leftmost s1 is optimal
@@ -240,9 +289,9 @@ struct StrPattern {
     uint64_t p8, m8;  // first min(n, 8) bytes, little endian, and their mask
 };
 
-__device__ __forceinline__ StrPattern make_pattern(const uint8_t* w, int n) {
+__device__ __forceinline__ StrPattern make_pattern(cptr<uint8_t> w, int n) {
     StrPattern P;
-    P.p8 = *reinterpret_cast<const uint64_t*>(w);  // bytes past n are zero
+    P.p8 = *(cptr<uint64_t>)w;  // bytes past n are zero
     P.m8 = n >= 8 ? ~uint64_t(0) : ((uint64_t(1) << (8 * n)) - 1);
     P.p8 &= P.m8;
     return P;
@@ -252,59 +301,156 @@ struct StrLds {
     uint32_t* offs;    // [257] row start offsets within the mini block's heap
     uint32_t* first1;  // [256] leftmost s1 start (0xffffffff: none)
     uint32_t* last2;   // [256] rightmost s2 start + 1 (0: none)
-    uint32_t* cand;    // [kCandCap] verified hits: pos << 2 | is_s1 | is_s2 << 1
 };
 
-// Maps the queued hits to their rows (binary search over the row offsets,
-// one hit per lane) and records leftmost s1 / rightmost s2 starts.
-__device__ __forceinline__ void resolve_hits(const StrLds& L, int ncand, const DevPred& p, const uint8_t* hs, int lane) {
-    wave_lds_sync();
-    for (int j = lane; j < ncand; j += kWave) {
-        const uint32_t e = L.cand[j], pos = e >> 2;
-        const int r = row_of(L.offs, pos);
-        const uint32_t rend = L.offs[r + 1];
-        if ((e & 1u) && pos + (uint32_t)p.n1 <= rend && (p.n1 <= 8 || bytes_eq(hs + pos, p.s1, 8, p.n1)))
-            atomicMin(&L.first1[r], pos);
-        if ((e & 2u) && pos + (uint32_t)p.n2 <= rend && (p.n2 <= 8 || bytes_eq(hs + pos, p.s2, 8, p.n2)))
-            atomicMax(&L.last2[r], pos + 1);
-    }
-    wave_lds_sync();
+// Records an s1 and/or s2 start at heap position pos of the mini block: the
+// row comes from a binary search over the row offsets; a word longer than 8
+// bytes is checked in full where it rests.
+__device__ __forceinline__ void note_start(const StrLds& L, uint32_t pos, bool m1, bool m2, CP& p,
+                                           cptr<uint8_t> hs) {
+    const int r = row_of(L.offs, pos);
+    const uint32_t rend = L.offs[r + 1];
+    if (m1 && pos + (uint32_t)p.n1 <= rend && (p.n1 <= 8 || bytes_eq(hs + pos, p.s1, 8, p.n1)))
+        atomicMin(&L.first1[r], pos);
+    if (m2 && pos + (uint32_t)p.n2 <= rend && (p.n2 <= 8 || bytes_eq(hs + pos, p.s2, 8, p.n2)))
+        atomicMax(&L.last2[r], pos + 1);
 }
 
-// Returns the 4-bit match mask of the lane's rows; clears ok on corruption.
-// kMasked: some word is shorter than 4 bytes, so 4-byte windows are masked.
-template <bool kMasked>
-__device__ __forceinline__ uint32_t str_pred(const DevCol& c, const DevPred& p, int m, int lane, int nvalid,
-                                             const StrLds& L, bool& ok) {
-    uint32_t* const offs = L.offs;
-    MbHdr h = mb_hdr(c, m);
-    const uint64_t h0 = c.hoff[m], h1 = c.hoff[m + 1];
-    if (!(h.ok && h0 <= h1 && h1 <= c.heap_bytes && (h1 - h0) < (uint64_t(1) << 30))) {
-        ok = false;
-        return 0;
+// Tests the 4 byte positions of one word (q = its byte offset from the
+// 16-byte-aligned start, e1/e2 = the two words after it) with 8-byte windows.
+__device__ __forceinline__ void check_word(const StrLds& L, uint32_t q, uint32_t e0, uint32_t e1, uint32_t e2,
+                                           uint32_t s0, uint32_t total, const StrPattern& P1, const StrPattern& P2,
+                                           CP& p, cptr<uint8_t> hs) {
+    uint32_t k1 = 0, k2 = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t lo = t ? __builtin_amdgcn_alignbit(e1, e0, 8 * t) : e0;
+        const uint32_t hi = t ? __builtin_amdgcn_alignbit(e2, e1, 8 * t) : e1;
+        const uint64_t win8 = (uint64_t)lo | ((uint64_t)hi << 32);
+        const uint32_t qt = q + t;
+        const bool inr = qt >= s0 && qt - s0 < total;
+        k1 |= (uint32_t)(inr && (win8 & P1.m8) == P1.p8) << t;
+        k2 |= (uint32_t)(inr && (win8 & P2.m8) == P2.p8) << t;
     }
-    const uint64_t a0 = h0 & ~uint64_t(15);
-    const uint32_t s0 = (uint32_t)(h0 - a0);
-    const uint4* g = reinterpret_cast<const uint4*>(c.heap + a0);
-    // Issue the first heap segment's loads before the length scan.
-    uint4 W[kSegIters];
-    const uint32_t span0 = s0 + (uint32_t)(h1 - h0);
-    const uint32_t nvec = (span0 + 15u) >> 4;
+    for (uint32_t k = k1 | k2; k; k &= k - 1) {
+        const int t = __builtin_ctz(k);
+        note_start(L, q + t - s0, (k1 >> t) & 1u, (k2 >> t) & 1u, p, hs);
+    }
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// One mini block's string test between issuing its loads and using them.
+struct StrTile {
+    uint4 W[kSegIters];    // heap segment: lane l holds bytes [16 (base + it * 64 + l), +16)
+    uint32_t tx, ty;       // lane 63: the two words after the segment
+    uint64_t lraw[4];      // packed lengths of rows 4 lane .. 4 lane + 3, unshifted
+    cptr<uint4> g;         // 16-byte-aligned start of the heap bytes
+    const uint8_t* gp;     // the same address, generic
+    uint64_t h0, h1;       // heap byte range of the mini block
+    int64_t lbase;         // minimum length
+    uint32_t lsh;          // bit offset of row 4 lane's length in lraw[0]
+    int b;                 // length bit width
+    bool ok;
+};
+
+// Buffer resource over [p, p + nbytes): raw (stride 0) 32-bit words; a load
+// whose VGPR offset + immediate offset lies past nbytes returns zeros.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+// Loads heap vectors base .. base + 511 of the tile (vector v = bytes
+// [16 v, 16 v + 16) from the 16-byte-aligned start) into W; vectors past
+// nvec read as zero through the buffer range check.  The per-lane offset is
+// the only VGPR address; the slots differ by immediate offsets.
+__device__ __forceinline__ void load_segment(StrTile& S, uint32_t base, uint32_t nvec, int lane) {
+    const uint32_t nbytes = (nvec + 1u - base) * 16u;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(S.gp + (uint64_t)base * 16u), 0, (int)nbytes, kRawBufferWord3);
+    // The empty asm keeps the compiler from hoisting one offset register per
+    // slot out of the loops: the slot offsets must stay immediates.
+    int vo = lane * 16;
+    asm volatile("" : "+v"(vo));
+    const int vo2 = vo + 4096;
 #pragma unroll
     for (int it = 0; it < kSegIters; ++it) {
-        uint32_t v = it * kWave + lane;
-        W[it] = v <= nvec ? g[v] : make_uint4(0u, 0u, 0u, 0u);
+        const int off = it * kWave * 16;  // below 4096: immediate on vo; else on vo2
+        const u32x4 t = off < 4096 ? __builtin_amdgcn_raw_buffer_load_b128(r, vo + off, 0, 0)
+                                   : __builtin_amdgcn_raw_buffer_load_b128(r, vo2 + (off - 4096), 0, 0);
+        S.W[it] = make_uint4(t.x, t.y, t.z, t.w);
     }
-    // Row offsets: lane l takes rows 4l..4l+3, so one wave scan suffices.
-    uint32_t len[4], lsum = 0;
+    const uint32_t vt = base + kSegIters * kWave;  // wave-uniform: scalar load
+    S.tx = S.ty = 0;
+    if (vt <= nvec) {
+        const u32x2 t = ((cptr<u32x2>)S.g)[2 * vt];
+        S.tx = t.x;
+        S.ty = t.y;
+    }
+}
+
+// Issues the loads of mini block m's lengths and first heap segment.
+__device__ __forceinline__ void str_begin(CC& c, int m, int lane, StrTile& S) {
+    const MbHdr h = mb_hdr(c, m);
+    S.h0 = ro(c.hoff)[m];
+    S.h1 = ro(c.hoff)[m + 1];
+    S.ok = h.ok && h.b <= 32 && S.h0 <= S.h1 && S.h1 <= c.heap_bytes && (S.h1 - S.h0) < (uint64_t(1) << 30);
+    S.b = S.ok ? h.b : 0;
+    S.lbase = h.base;
+    const uint64_t a0 = S.h0 & ~uint64_t(15);
+    S.g = (cptr<uint4>)(c.heap + a0);
+    S.gp = c.heap + a0;
+    const uint32_t nvec = S.ok ? (uint32_t)((S.h1 - a0 + 15u) >> 4) : 0u;
+    // lengths: row 4 lane + j at bit (4 lane + j) b; one 8-byte window per row
+    const uint32_t bp = 4u * (uint32_t)lane * (uint32_t)S.b;
+    S.lsh = bp & 31u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        int i = 4 * lane + j;
-        uint32_t u = h.b ? (uint32_t)bits_at(h.w, (uint32_t)i * (uint32_t)h.b, h.b) : 0u;
-        len[j] = i < nvalid ? (uint32_t)h.base + u : 0u;
+        const uint32_t pj = bp + (uint32_t)j * (uint32_t)S.b;
+        S.lraw[j] = S.b ? *(cptr<u64_a4>)(h.w + (pj >> 5)) : 0;
+    }
+    if (S.ok) {
+        load_segment(S, 0, nvec, lane);
+    } else {
+#pragma unroll
+        for (int it = 0; it < kSegIters; ++it) S.W[it] = make_uint4(0u, 0u, 0u, 0u);
+        S.tx = S.ty = 0;
+    }
+}
+
+// Neighbour words of lane's segment slot it: the next lane's first two words
+// (for lane 63, those of the next slot's lane 0, or the words after the
+// segment).
+__device__ __forceinline__ void next_words(const StrTile& S, int it, int lane, uint32_t& nx, uint32_t& nx2) {
+    nx = dpp_u32<kDppWaveShl1>(S.W[it].x);
+    nx2 = dpp_u32<kDppWaveShl1>(S.W[it].y);
+    uint32_t lx = S.tx, ly = S.ty;
+    if (it + 1 < kSegIters) {
+        lx = __builtin_amdgcn_readlane(S.W[it + 1 < kSegIters ? it + 1 : it].x, 0);
+        ly = __builtin_amdgcn_readlane(S.W[it + 1 < kSegIters ? it + 1 : it].y, 0);
+    }
+    if (lane == kWave - 1) { nx = lx; nx2 = ly; }
+}
+
+// Returns the 4-bit match mask of the lane's rows (row 64 k + lane -> bit k)
+// for the mini block whose loads str_begin issued; clears ok on corruption.
+// kMasked: some word is shorter than 4 bytes, so 4-byte windows are masked.
+template <bool kMasked>
+__device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvalid, StrTile& S,
+                                               const StrLds& L, bool& ok) {
+    if (!S.ok) { ok = false; return 0; }
+    uint32_t* const offs = L.offs;
+    const uint32_t s0 = (uint32_t)(S.h0 & 15u);
+    const uint32_t nvec = (uint32_t)((S.h1 - (S.h0 - s0) + 15u) >> 4);
+    // Row offsets: lane l takes rows 4l..4l+3, so one wave scan suffices.
+    uint32_t len[4], lsum = 0;
+    const uint64_t lmask = (uint64_t(1) << S.b) - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t sh = (S.lsh + (uint32_t)j * (uint32_t)S.b) & 31u;
+        const uint32_t u = (uint32_t)((S.lraw[j] >> sh) & lmask);
+        len[j] = 4 * lane + j < nvalid ? (uint32_t)S.lbase + u : 0u;
         lsum += len[j];
     }
-    const uint32_t incl = wave_incl_scan_u32(lsum, lane);
+    const uint32_t incl = wave_incl_scan_u32(lsum);
     const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
     {
         uint32_t o = incl - lsum;
@@ -318,28 +464,21 @@ __device__ __forceinline__ uint32_t str_pred(const DevCol& c, const DevPred& p, 
         reinterpret_cast<uint4*>(L.last2)[lane] = make_uint4(0u, 0u, 0u, 0u);
     }
     if (lane == 0) offs[256] = total;
-    if ((uint64_t)total != h1 - h0) { ok = false; return 0; }
+    if ((uint64_t)total != S.h1 - S.h0) { ok = false; return 0; }
 
     const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
     const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;  // first 4 bytes
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
-    const uint8_t* hs = c.heap + h0;
-    int ncand = 0;
+    cptr<uint8_t> hs = ro(c.heap + S.h0);
     for (uint32_t base = 0;; base += kSegIters * kWave) {
-        // Hot loop: bit (4 * it + wd) of hits marks a word of the lane whose
-        // 4-byte window matched a prefix at one of its byte positions.
+        // Hot loop: bit (4 it + wd) of hits marks a word whose 4-byte windows
+        // match a prefix.
         uint32_t hits = 0;
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
-            const uint4 w = W[it];
-            uint32_t nx = __shfl_down(w.x, 1u, kWave);
-            if (it + 1 < kSegIters) {
-                const uint32_t lx = __builtin_amdgcn_readlane(W[it + 1 < kSegIters ? it + 1 : it].x, 0);
-                if (lane == 63) nx = lx;
-            } else {
-                const uint32_t v = base + kSegIters * kWave;
-                if (lane == 63) nx = v <= nvec ? g[v].x : 0u;
-            }
+            const uint4 w = S.W[it];
+            uint32_t nx, nx2;
+            next_words(S, it, lane, nx, nx2);
             const uint32_t e[5] = {w.x, w.y, w.z, w.w, nx};
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
@@ -357,52 +496,29 @@ __device__ __forceinline__ uint32_t str_pred(const DevCol& c, const DevPred& p, 
                 hits |= hit ? (1u << (4 * it + wd)) : 0u;
             }
         }
-        // Rare path: re-read each hit word with its successors (L1/L2 hits),
-        // check 8-byte windows and queue verified starts.
-        for (;;) {
-            const bool have = hits != 0u;
-            if (__ballot(have) == 0) break;
-            uint32_t e0 = 0, e1 = 0, e2 = 0, q = 0;
-            if (have) {
-                const int j = __builtin_ctz(hits);
-                hits &= hits - 1;
-                const int it = j >> 2, wd = j & 3;
-                const uint32_t v = base + (uint32_t)it * kWave + (uint32_t)lane;
-                const uint4 x = g[v], y = g[v + 1];
-                const uint32_t f[6] = {x.x, x.y, x.z, x.w, y.x, y.y};
-                e0 = wd == 0 ? f[0] : wd == 1 ? f[1] : wd == 2 ? f[2] : f[3];
-                e1 = wd == 0 ? f[1] : wd == 1 ? f[2] : wd == 2 ? f[3] : f[4];
-                e2 = wd == 0 ? f[2] : wd == 1 ? f[3] : wd == 2 ? f[4] : f[5];
-                q = v * 16u + 4u * (uint32_t)wd;
-            }
+        // Rare path: the hit words are checked from the same registers.
+        if (__ballot(hits != 0)) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t lo = t ? __builtin_amdgcn_alignbit(e1, e0, 8 * t) : e0;
-                const uint32_t hi = t ? __builtin_amdgcn_alignbit(e2, e1, 8 * t) : e1;
-                const uint64_t win8 = (uint64_t)lo | ((uint64_t)hi << 32);
-                const uint32_t qt = q + t;
-                const bool inr = have && qt >= s0 && qt - s0 < total;
-                const bool v1 = inr && (win8 & P1.m8) == P1.p8;
-                const bool v2 = inr && (win8 & P2.m8) == P2.p8;
-                const bool emit = v1 || v2;
-                const uint64_t bal = __ballot(emit);
-                if (emit) L.cand[ncand + bits_below(bal)] = ((qt - s0) << 2) | (uint32_t)v1 | ((uint32_t)v2 << 1);
-                ncand += (int)__popcll(bal);
-                if (ncand > kCandCap - kWave) {
-                    resolve_hits(L, ncand, p, hs, lane);
-                    ncand = 0;
+            for (int it = 0; it < kSegIters; ++it) {
+                uint32_t hm = (hits >> (4 * it)) & 0xFu;
+                if (__ballot(hm != 0) == 0) continue;
+                const uint4 w = S.W[it];
+                uint32_t nx, nx2;
+                next_words(S, it, lane, nx, nx2);
+                const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
+                while (hm) {
+                    const int wd = __builtin_ctz(hm);
+                    hm &= hm - 1;
+                    const uint32_t e0 = wd == 0 ? w.x : wd == 1 ? w.y : wd == 2 ? w.z : w.w;
+                    const uint32_t e1 = wd == 0 ? w.y : wd == 1 ? w.z : wd == 2 ? w.w : nx;
+                    const uint32_t e2 = wd == 0 ? w.z : wd == 1 ? w.w : wd == 2 ? nx : nx2;
+                    check_word(L, q0 + 4u * (uint32_t)wd, e0, e1, e2, s0, S.h1 - S.h0, P1, P2, p, hs);
                 }
             }
         }
         if (base + kSegIters * kWave >= nvec) break;
-        const uint32_t nb = base + kSegIters * kWave;
-#pragma unroll
-        for (int it = 0; it < kSegIters; ++it) {
-            uint32_t v = nb + it * kWave + lane;
-            W[it] = v <= nvec ? g[v] : make_uint4(0u, 0u, 0u, 0u);
-        }
+        load_segment(S, base + kSegIters * kWave, nvec, lane);
     }
-    if (ncand) resolve_hits(L, ncand, p, hs, lane);
     wave_lds_sync();
     uint32_t res = 0;
 #pragma unroll
@@ -413,6 +529,14 @@ __device__ __forceinline__ uint32_t str_pred(const DevCol& c, const DevPred& p, 
         res |= (uint32_t)hit << k;
     }
     return res;
+}
+
+template <bool kMasked>
+__device__ __forceinline__ uint32_t str_pred(CC& c, CP& p, int m, int lane, int nvalid, const StrLds& L,
+                                             bool& ok) {
+    StrTile S;
+    str_begin(c, m, lane, S);
+    return str_finish<kMasked>(c, p, lane, nvalid, S, L, ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,13 +573,14 @@ __device__ __forceinline__ uint32_t hash32(int32_t key, int log2cap) {
 
 // Linear-probing lookup; returns the slot or -1.
 template <bool kLds>
-__device__ __forceinline__ int hash_find(const DevHash& h, const uint8_t* smem_shared, int64_t key) {
+__device__ __forceinline__ int hash_find(CH& h, const uint8_t* smem_shared, int64_t key) {
     if (key < INT32_MIN || key > INT32_MAX || key == kEmptyKey) return -1;
     const int32_t k = (int32_t)key;
-    const int32_t* keys = kLds ? reinterpret_cast<const int32_t*>(smem_shared + h.lds_off) : h.keys;
+    const int32_t* lkeys = reinterpret_cast<const int32_t*>(smem_shared + h.lds_off);
+    cptr<int32_t> gkeys = ro(h.keys);
     uint32_t s = hash32(k, h.log2cap);
     for (uint32_t n = 0; n <= h.cap_mask; ++n) {
-        int32_t x = keys[s];
+        int32_t x = kLds ? lkeys[s] : gkeys[s];
         if (x == k) return (int)s;
         if (x == kEmptyKey) return -1;
         s = (s + 1) & h.cap_mask;
@@ -464,27 +589,26 @@ __device__ __forceinline__ int hash_find(const DevHash& h, const uint8_t* smem_s
 }
 
 template <bool kLds>
-__device__ __forceinline__ int64_t hash_payload(const DevHash& h, const uint8_t* smem_shared, int k,
+__device__ __forceinline__ int64_t hash_payload(CH& h, const uint8_t* smem_shared, int k,
                                                 int slot) {
-    const uint8_t* base;
     if (kLds) {
         // payload arrays follow the keys at the same relative offsets
-        base = smem_shared + h.lds_off + ((const uint8_t*)h.pay[k] - (const uint8_t*)h.keys);
-    } else {
-        base = (const uint8_t*)h.pay[k];
+        const uint8_t* base = smem_shared + h.lds_off + ((const uint8_t*)h.pay[k] - (const uint8_t*)h.keys);
+        return h.pay64[k] ? reinterpret_cast<const int64_t*>(base)[slot]
+                          : (int64_t)reinterpret_cast<const int32_t*>(base)[slot];
     }
-    return h.pay64[k] ? reinterpret_cast<const int64_t*>(base)[slot]
-                      : (int64_t)reinterpret_cast<const int32_t*>(base)[slot];
+    cptr<uint8_t> base = ro((const uint8_t*)h.pay[k]);
+    return h.pay64[k] ? ((cptr<int64_t>)base)[slot] : (int64_t)((cptr<int32_t>)base)[slot];
 }
 
 // ---------------------------------------------------------------------------
 // Aggregation of one surviving row into the (LDS or global) group table
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ __forceinline__ bool group_index(const DevQuery& Q, const S& sv, int64_t& g) {
+__device__ __forceinline__ bool group_index(CQ& Q, const S& sv, int64_t& g) {
     g = 0;
     for (int k = 0; k < Q.nkeys; ++k) {
-        const DevKey& K = Q.keys[k];
+        CK& K = Q.keys[k];
         int64_t d = sv.get(K.slot) - K.min;
         if (d < 0 || d >= K.card) return false;
         g += d * K.stride;
@@ -493,10 +617,10 @@ __device__ __forceinline__ bool group_index(const DevQuery& Q, const S& sv, int6
 }
 
 template <class S>
-__device__ __forceinline__ int64_t acc_value(const DevAcc& A, const S& sv) {
+__device__ __forceinline__ int64_t acc_value(CA& A, const S& sv) {
     int64_t prod = 1;
     for (int t = 0; t < A.nterms; ++t) {
-        const DevTerm& T = A.t[t];
+        CT& T = A.t[t];
         int64_t x = T.slot >= 0 ? T.mul * sv.get(T.slot) + T.add : T.add;
         prod *= x;
     }
@@ -504,7 +628,7 @@ __device__ __forceinline__ int64_t acc_value(const DevAcc& A, const S& sv) {
 }
 
 template <class S>
-__device__ __forceinline__ void aggregate_row(const DevQuery& Q, uint8_t* smem_shared, const S& sv,
+__device__ __forceinline__ void aggregate_row(CQ& Q, uint8_t* smem_shared, const S& sv,
                                               int64_t g) {
     const int nacc = Q.nacc;
     unsigned long long* T = Q.agg_lds
@@ -518,15 +642,15 @@ __device__ __forceinline__ void aggregate_row(const DevQuery& Q, uint8_t* smem_s
 // Stage B: probes, value loads and aggregation of one row per lane.  m and i
 // may differ between lanes (rows queued from several mini blocks).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void stage_b(const DevQuery& Q, uint8_t* smem_shared, LdsSlots sv, int m, int i,
+__device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv, int m, int i,
                                         bool active, bool& ok_hdr) {
     bool ok = active;
     const int nprobes = Q.nprobes;
     for (int j = 0; j < nprobes; ++j) {
         if (__ballot(ok) == 0) return;
-        const DevProbe& P = Q.probes[j];
+        CPR& P = Q.probes[j];
         if (ok) {
-            const DevCol& fc = Q.cols[P.fk_col];
+            CC& fc = Q.cols[P.fk_col];
             int64_t fk = decode_at(fc, m, i, ok_hdr);
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, ok_hdr);
             const bool lds = P.h.lds_off >= 0;
@@ -548,8 +672,8 @@ __device__ __forceinline__ void stage_b(const DevQuery& Q, uint8_t* smem_shared,
 #pragma unroll
     for (int s = 0; s < kMaxSlots; ++s) {
         if (s < nloads) {
-            const DevLoad& Ld = Q.loads[s];
-            const DevCol& c = Q.cols[Ld.col];
+            CL& Ld = Q.loads[s];
+            CC& c = Q.cols[Ld.col];
             int64_t x = decode_at(c, m, i, ok_hdr);
             if (Ld.dict_val) x = dict_value(c, x, ok_hdr);
             sv.set(s, x);
@@ -569,10 +693,9 @@ struct WaveArea {
     uint32_t* offs;    // [260] string row offsets
     uint32_t* first1;  // [256] leftmost s1 start per row
     uint32_t* last2;   // [256] rightmost s2 start + 1 per row
-    uint32_t* cand;    // [kCandCap] string-predicate hits awaiting their row
 };
 
-__device__ __forceinline__ void flush_pending(const DevQuery& Q, uint8_t* smem_shared, const WaveArea& W, int& npend, int lane,
+__device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int& npend, int lane,
                               bool& ok_hdr) {
     wave_lds_sync();
     for (int base = 0; base < npend; base += kWave) {
@@ -585,7 +708,45 @@ __device__ __forceinline__ void flush_pending(const DevQuery& Q, uint8_t* smem_s
     wave_lds_sync();
 }
 
-__device__ __forceinline__ void process_tile(const DevQuery& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
+// Stage A of mini block m: returns the mask of rows passing every atom (row
+// 64 k + lane -> bit k).  kEager: the plan's one string atom comes last and
+// its loads are issued before the integer atoms run, so both wait for memory
+// once, together.
+template <bool kEager>
+__device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m, int lane, int nvalid,
+                                                bool& ok_hdr) {
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
+    const StrLds L{W.offs, W.first1, W.last2};
+    const int npreds = Q.npreds;
+    CP& PL = Q.preds[npreds - 1];
+    StrTile S;
+    if (kEager) str_begin(Q.cols[PL.col], m, lane, S);
+    int64_t v[4];
+    int last_col = -1;
+    for (int a = 0; a < (kEager ? npreds - 1 : npreds); ++a) {
+        CP& P = Q.preds[a];
+        if (!kEager && P.kind == PK_STR) {
+            if (P.n1 >= 4 && P.n2 >= 4) mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            else mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+        } else {
+            if (P.col != last_col) {
+                ok_hdr &= decode_dense(Q.cols[P.col], m, lane, v);
+                last_col = P.col;
+            }
+            mask &= eval_int_pred(P, Q.in_vals, v);
+        }
+        if (__ballot(mask != 0) == 0) return 0;  // no survivor in this mini block
+    }
+    if (kEager) {
+        if (PL.n1 >= 4 && PL.n2 >= 4) mask &= str_finish<false>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+        else mask &= str_finish<true>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+    }
+    return mask;
+}
+
+__device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
                              int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
     const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
@@ -601,27 +762,10 @@ __device__ __forceinline__ void process_tile(const DevQuery& Q, uint8_t* smem_sh
         return;
     }
 
-    uint32_t mask = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
-
-    int64_t v[4];
-    int last_col = -1;
-    for (int a = 0; a < npreds; ++a) {
-        const DevPred& P = Q.preds[a];
-        if (P.kind == PK_STR) {
-            const StrLds L{W.offs, W.first1, W.last2, W.cand};
-            if (P.n1 >= 4 && P.n2 >= 4) mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
-            else mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
-        } else {
-            if (P.col != last_col) {
-                ok_hdr &= decode_dense(Q.cols[P.col], m, lane, v);
-                last_col = P.col;
-            }
-            mask &= eval_int_pred(P, Q.in_vals, v);
-        }
-        if (__ballot(mask != 0) == 0) return;  // no survivor in this mini block
-    }
+    const uint32_t mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
+                              ? filter_tile<true>(Q, W, m, lane, nvalid, ok_hdr)
+                              : filter_tile<false>(Q, W, m, lane, nvalid, ok_hdr);
+    if (__ballot(mask != 0) == 0) return;
 
     // Queue survivors (wave ballot + mbcnt compaction).
 #pragma unroll
@@ -634,25 +778,30 @@ __device__ __forceinline__ void process_tile(const DevQuery& Q, uint8_t* smem_sh
     if (npend >= kWave) flush_pending(Q, smem_shared, W, npend, lane, ok_hdr);
 }
 
-// Per-wave LDS: stage-B slots, then (plans with fact predicates) the
-// survivor queue, then (string predicates) row offsets, s1 and s2 starts.
+// Per-wave LDS: (plans with fact predicates) the survivor queue, then one
+// region shared by the stage-B value slots and the string predicate's row
+// offsets, s1 / s2 starts and hit queue -- a wave never uses both at once
+// (a mini block's string test finishes before its survivors are queued).
+constexpr size_t kSlotBytes = kMaxSlots * kWave * 8;
+constexpr size_t kStrBytes = 260 * 4 + 2 * 256 * 4;
+
 __host__ __device__ constexpr size_t wave_area_bytes(bool str_stage, bool pend_stage) {
-    return kMaxSlots * kWave * 8 + (pend_stage ? kPendCap * 4 : 0) + (str_stage ? (260 * 4 + 2 * 256 * 4 + kCandCap * 4) : 0);
+    return (pend_stage ? kPendCap * 4 : 0) + (str_stage && kStrBytes > kSlotBytes ? kStrBytes : kSlotBytes);
 }
 
 __device__ __forceinline__ WaveArea wave_area(uint8_t* p, bool pend_stage) {
     WaveArea W;
-    W.slots = reinterpret_cast<int64_t*>(p);
-    W.pend = reinterpret_cast<uint32_t*>(p + kMaxSlots * kWave * 8);
-    W.offs = W.pend + (pend_stage ? kPendCap : 0);
+    W.pend = reinterpret_cast<uint32_t*>(p);
+    uint8_t* shared = p + (pend_stage ? kPendCap * 4 : 0);
+    W.slots = reinterpret_cast<int64_t*>(shared);
+    W.offs = reinterpret_cast<uint32_t*>(shared);
     W.first1 = W.offs + 260;
     W.last2 = W.first1 + 256;
-    W.cand = W.last2 + 256;
     return W;
 }
 
 // Merge the workgroup's LDS group table into the plan's global table.
-__device__ void flush_lds_agg(const DevQuery& Q, uint8_t* smem_shared) {
+__device__ void flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
     if (!Q.agg_lds) return;
     const int64_t n = Q.ngroups * Q.nacc;
     unsigned long long* T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off);
@@ -664,13 +813,13 @@ __device__ void flush_lds_agg(const DevQuery& Q, uint8_t* smem_shared) {
 }
 
 // Load a plan's LDS-resident dimension tables and clear its LDS group table.
-__device__ void load_lds_state(const DevQuery& Q, uint8_t* smem_shared) {
+__device__ void load_lds_state(CQ& Q, uint8_t* smem_shared) {
     for (int j = 0; j < Q.nprobes; ++j) {
-        const DevHash& h = Q.probes[j].h;
+        CH& h = Q.probes[j].h;
         if (h.lds_off < 0) continue;
-        const uint4* src = reinterpret_cast<const uint4*>(h.keys);
+        cptr<uint4> src = (cptr<uint4>)h.keys;
         uint4* dst = reinterpret_cast<uint4*>(smem_shared + h.lds_off);
-        for (uint32_t e = threadIdx.x; e < h.bytes / 16u; e += blockDim.x) dst[e] = src[e];
+        for (uint32_t e = threadIdx.x; e < h.bytes / 16u; e += blockDim.x) dst[e] = ld4(src, e);
     }
     if (Q.agg_lds) {
         const int64_t n = Q.ngroups * Q.nacc;
@@ -687,7 +836,7 @@ __device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p
 // host buffer (paper Section 3.1: the aggregate is converted into a record
 // format and returned to the host), then clear the device table for the next
 // execution.  Run by one workgroup after every other one has finished.
-__device__ void emit_records(const DevQuery& Q, int32_t* ctrl) {
+__device__ void emit_records(CQ& Q, int32_t* ctrl) {
     const int nacc = Q.nacc;
     const int64_t G = Q.ngroups;
     unsigned long long* T = reinterpret_cast<unsigned long long*>(Q.agg);
@@ -743,12 +892,12 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         int qi = 0;
         while (qi + 1 < a.nq && a.item_start[qi + 1] <= item) ++qi;
         qi = uniform_i32(qi);
-        const DevQuery& Q = *a.q[qi];
+        CQ& Q = *ro(a.q[qi]);
         if (qi != cur) {
             if (cur >= 0) {
                 __syncthreads();
-                flush_lds_agg(*a.q[cur], shared_area);
-                if (!ok_hdr) atomicOr(a.q[cur]->status, ST_CORRUPT);
+                flush_lds_agg(*ro(a.q[cur]), shared_area);
+                if (!ok_hdr) atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
                 ok_hdr = true;
             }
             __syncthreads();
@@ -763,8 +912,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
     }
     if (cur >= 0) {
         __syncthreads();
-        flush_lds_agg(*a.q[cur], shared_area);
-        if (!ok_hdr) atomicOr(a.q[cur]->status, ST_CORRUPT);
+        flush_lds_agg(*ro(a.q[cur]), shared_area);
+        if (!ok_hdr) atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
     }
     // Last workgroup out emits every plan's records and resets the queue.
     __threadfence();
@@ -773,7 +922,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
     __syncthreads();
     if ((uint32_t)ctrl[1] != gridDim.x - 1) return;
     __threadfence();
-    for (int qi = 0; qi < a.nq; ++qi) emit_records(*a.q[qi], ctrl);
+    for (int qi = 0; qi < a.nq; ++qi) emit_records(*ro(a.q[qi]), ctrl);
     if (threadIdx.x == 0) {
         __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -784,23 +933,23 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
 // ---------------------------------------------------------------------------
 // Hash build (dimension scan -> filter -> insert)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t hash_tile_mask(const HashBuildArgs& A, int m, int lane, int nvalid,
+__device__ __forceinline__ uint32_t hash_tile_mask(CHB& A, int m, int lane, int nvalid,
                                                    int64_t key[4], int64_t pay[2][4], bool& ok) {
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
     int64_t v[4];
     for (int p = 0; p < A.npreds; ++p) {
-        const DevPred& P = A.preds[p];
+        CP& P = A.preds[p];
         ok &= decode_dense(A.cols[P.col], m, lane, v);
         mask &= eval_int_pred(P, A.in_vals, v);
     }
-    const DevCol& kc = A.cols[A.key_col];
+    CC& kc = A.cols[A.key_col];
     ok &= decode_dense(kc, m, lane, key);
     if (kc.enc == ENC_DICT)
         for (int k = 0; k < 4; ++k) key[k] = dict_value(kc, key[k], ok);
     for (int j = 0; j < A.npay; ++j) {
-        const DevCol& pc = A.cols[A.pay_col[j]];
+        CC& pc = A.cols[A.pay_col[j]];
         ok &= decode_dense(pc, m, lane, pay[j]);
         if (pc.enc == ENC_DICT)
             for (int k = 0; k < 4; ++k) pay[j][k] = dict_value(pc, pay[j][k], ok);
@@ -809,7 +958,7 @@ __device__ __forceinline__ uint32_t hash_tile_mask(const HashBuildArgs& A, int m
 }
 
 __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs* __restrict__ args) {
-    const HashBuildArgs& A = *args;
+    CHB& A = *ro(args);
     const int lane = lane_id();
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -840,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs*
 }
 
 __global__ __launch_bounds__(kBlock) void hash_insert_kernel(const HashBuildArgs* __restrict__ args) {
-    const HashBuildArgs& A = *args;
+    CHB& A = *ro(args);
     const int lane = lane_id();
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -890,8 +1039,8 @@ __global__ void fill_kernel(T* p, T v, int64_t n) {
 // ---------------------------------------------------------------------------
 // Decode one integer column to int64 (codes for DICT).
 __global__ __launch_bounds__(kBlock) void frag_decode_int(const DevQuery* __restrict__ q, int c, int64_t* out) {
-    const DevQuery& Q = *q;
-    const DevCol& C = Q.cols[c];
+    CQ& Q = *ro(q);
+    CC& C = Q.cols[c];
     const int lane = lane_id();
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -910,8 +1059,8 @@ __global__ __launch_bounds__(kBlock) void frag_decode_int(const DevQuery* __rest
 // Decode a string column: offsets [nrows + 1] and a copy of the bytes.
 __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __restrict__ q, int c, int64_t* off,
                                                            uint8_t* bytes) {
-    const DevQuery& Q = *q;
-    const DevCol& C = Q.cols[c];
+    CQ& Q = *ro(q);
+    CC& C = Q.cols[c];
     const int lane = lane_id();
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -920,13 +1069,13 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
         const int nvalid = (int)min((int64_t)kMB, Q.nrows - (int64_t)m * kMB);
         MbHdr h = mb_hdr(C, m);
         ok &= h.ok;
-        uint64_t h0 = C.hoff[m], h1 = C.hoff[m + 1];
+        uint64_t h0 = ro(C.hoff)[m], h1 = ro(C.hoff)[m + 1];
         if (!(h0 <= h1 && h1 <= C.heap_bytes)) { ok = false; continue; }
         uint64_t carry = h0;
         for (int k = 0; k < 4; ++k) {
             int i = 64 * k + lane;
             uint64_t len = (i < nvalid) ? (uint64_t)h.base + (h.b ? bits_at(h.w, (uint32_t)i * h.b, h.b) : 0) : 0;
-            uint64_t s = wave_incl_scan_u64(len, lane);
+            uint64_t s = wave_incl_scan_u64(len);
             if (i < nvalid) off[(int64_t)m * kMB + i] = (int64_t)(carry + s - len);
             carry += readlane_u64(s, 63);
         }
@@ -934,13 +1083,13 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
         // copy the bytes: 16-byte pieces where both sides are aligned
         uint64_t b = h0;
         while (b < h1 && (b & 15)) {
-            if (b + lane < h1 && ((b + lane) & ~uint64_t(15)) == (b & ~uint64_t(15))) bytes[b + lane] = C.heap[b + lane];
+            if (b + lane < h1 && ((b + lane) & ~uint64_t(15)) == (b & ~uint64_t(15))) bytes[b + lane] = ro(C.heap)[b + lane];
             b = (b | 15) + 1;
         }
         for (uint64_t v = b + 16 * (uint64_t)lane; v + 16 <= h1; v += 16 * kWave)
-            *reinterpret_cast<uint4*>(bytes + v) = *reinterpret_cast<const uint4*>(C.heap + v);
+            *reinterpret_cast<uint4*>(bytes + v) = ld4((cptr<uint4>)(C.heap + v), 0);
         uint64_t tail = b + ((h1 > b ? h1 - b : 0) & ~uint64_t(15));
-        if (tail + lane < h1) bytes[tail + lane] = C.heap[tail + lane];
+        if (tail + lane < h1) bytes[tail + lane] = ro(C.heap)[tail + lane];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) off[Q.nrows] = (int64_t)Q.cols[c].heap_bytes;
     if (!ok) atomicOr(Q.status, ST_CORRUPT);
@@ -948,8 +1097,8 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
 
 __global__ void frag_filter_int(const DevQuery* __restrict__ q, int pi, const int64_t* vals, uint8_t* flags,
                                 int first) {
-    const DevQuery& Q = *q;
-    const DevPred& P = Q.preds[pi];
+    CQ& Q = *ro(q);
+    CP& P = Q.preds[pi];
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < Q.nrows;
          r += (int64_t)gridDim.x * blockDim.x) {
         int64_t v4[4] = {vals[r], 0, 0, 0};
@@ -960,8 +1109,8 @@ __global__ void frag_filter_int(const DevQuery* __restrict__ q, int pi, const in
 
 __global__ void frag_filter_str(const DevQuery* __restrict__ q, int pi, const int64_t* off, const uint8_t* bytes,
                                 uint8_t* flags, int first) {
-    const DevQuery& Q = *q;
-    const DevPred& P = Q.preds[pi];
+    CQ& Q = *ro(q);
+    CP& P = Q.preds[pi];
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < Q.nrows;
          r += (int64_t)gridDim.x * blockDim.x) {
         bool prev = first ? true : flags[r] != 0;
@@ -976,7 +1125,7 @@ __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restric
                                                        int32_t* rows, unsigned long long* count) {
     __shared__ uint32_t wcnt[kWaves + 1];
     __shared__ unsigned long long base_s;
-    const DevQuery& Q = *q;
+    CQ& Q = *ro(q);
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     for (int64_t b0 = (int64_t)blockIdx.x * 1024; b0 < Q.nrows; b0 += (int64_t)gridDim.x * 1024) {
         bool f[4];
@@ -1007,7 +1156,7 @@ __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restric
 
 // all rows -> row list (plans without a fact predicate)
 __global__ void frag_iota(const DevQuery* __restrict__ q, int32_t* rows, unsigned long long* count) {
-    const DevQuery& Q = *q;
+    CQ& Q = *ro(q);
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < Q.nrows;
          r += (int64_t)gridDim.x * blockDim.x)
         rows[r] = (int32_t)r;
@@ -1020,8 +1169,8 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
                                                      const int32_t* rin, const unsigned long long* nin,
                                                      int32_t* rout, unsigned long long* nout,
                                                      const FragBuffers fb, int src, int npay_before) {
-    const DevQuery& Q = *q;
-    const DevProbe& P = Q.probes[j];
+    CQ& Q = *ro(q);
+    CPR& P = Q.probes[j];
     const int lane = lane_id();
     const int64_t n = (int64_t)*nin;
     for (int64_t b0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~63ll; b0 < n;
@@ -1032,7 +1181,7 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
         int32_t r = act ? rin[e] : 0;
         if (act) {
             int64_t fk = fkvals[r];
-            const DevCol& fc = Q.cols[P.fk_col];
+            CC& fc = Q.cols[P.fk_col];
             bool okd = true;
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, okd);
             slot = hash_find<false>(P.h, nullptr, fk);
@@ -1059,7 +1208,7 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
                                                          const unsigned long long* nrows_list, const FragBuffers fb,
                                                          int src) {
     __shared__ unsigned long long tab[4096];
-    const DevQuery& Q = *q;
+    CQ& Q = *ro(q);
     const int64_t n = (int64_t)*nrows_list;
     const bool local = Q.ngroups * Q.nacc <= 4096;
     if (local)
@@ -1079,7 +1228,7 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
             }
         }
         for (int l = 0; l < Q.nloads; ++l) {
-            const DevLoad& Ld = Q.loads[l];
+            CL& Ld = Q.loads[l];
             int64_t x = fb.dec[Ld.col][r];
             if (Ld.dict_val) x = dict_value(Q.cols[Ld.col], x, okall);
             sv.set(l, x);
@@ -1100,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
 __global__ __launch_bounds__(kBlock) void frag_emit(const DevQuery* __restrict__ q) {
     __shared__ int32_t ctrl[4];
     __threadfence();
-    emit_records(*q, ctrl);
+    emit_records(*ro(q), ctrl);
     __threadfence_system();
 }
 
