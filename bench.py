@@ -12,6 +12,13 @@ kernel's roofline (algorithmic compressed bytes per launch / average kernel
 time from HIP events on the launch stream, against 8 TB/s), the fragmented
 multi-kernel execution of the same plan, and the CPU oracle timed on the host
 over the same table (which also checks the GPU result bit-exactly).
+
+Other workloads (``--workload``): ``fa`` (1,000,000-row filter-aggregate),
+``sj`` (120,000,000-row star-join probe), ``mix`` (64 queries over a pool of
+filter-aggregate and star-join tables in ONE fused launch, against 64 solo
+launches and the fragmented path, plus the launch-knob tuner) and ``serve``
+(Poisson arrivals through the serving loop: completed QPS and p50/p99
+latency).
 """
 from __future__ import annotations
 
@@ -59,7 +66,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="wide", choices=["wide", "fa", "sj"])
+    ap.add_argument("--workload", default="wide", choices=["wide", "fa", "sj", "mix", "serve"])
+    ap.add_argument("--no-tune", action="store_true", help="mix: skip the knob sweep")
+    ap.add_argument("--qps", default="50,100,200,500", help="serve: arrival rates")
+    ap.add_argument("--seconds", type=float, default=30.0, help="serve: run time per rate")
+    ap.add_argument("--resident-rows", type=int, default=600_000_000, help="serve: resident fact rows")
+    ap.add_argument("--host-rows", type=int, default=0, help="serve: host-mapped fact rows (0: none)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--frag-steps", type=int, default=3)
     ap.add_argument("--no-oracle", action="store_true")
@@ -72,6 +84,11 @@ def main():
         print("bench.py measures one GPU: this build runs the fused path on a single MI355X "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "mix":
+        return bench_mix(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
     import oracle
@@ -188,6 +205,288 @@ def main():
                      "kernel": "fused_kernel", "kernel_ms": kern_ms},
         "fragmented": frag,
         "fused_speedup_vs_fragmented": (frag["ms_per_step"] / ms_per_step) if frag else None,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def referenced_columns(spec: dict) -> list:
+    used = [p["col"] for p in spec.get("filters", [])] + [p["fk"] for p in spec.get("probes", [])]
+    used += [r["col"] for r in spec.get("group_by", []) if "col" in r]
+    used += [t["ref"]["col"] for a in spec["aggs"] for t in a.get("terms", []) if "ref" in t and "col" in t["ref"]]
+    return list(dict.fromkeys(used))
+
+
+def mix_tables(scale: float = 1.0):
+    """The config-4 pool: 4 filter-aggregate and 4 star-join fact tables
+    (log-uniform sizes in [1M, 120M]) sharing one set of dimensions."""
+    from datagen import workloads as W
+    M = W.mix_plan(seed=4)
+    dims = W.sj_dims(seed=3)
+    tables = dict(dims)
+    encs = {}
+    for t, n in enumerate(M["fa_sizes"]):
+        tables[f"fa{t}"] = W.fa_table(max(256, int(n * scale)), seed=400 + t)
+        encs[f"fa{t}"] = W.FA_ENCODINGS
+    for t, n in enumerate(M["sj_sizes"]):
+        tables[f"sj{t}"] = W.sj_fact(max(256, int(n * scale)), seed=440 + t, dims=dims, name=f"sj{t}")
+    return M, tables, encs
+
+
+def bench_mix(args):
+    """Config 4: 64 queries in one fused launch vs 64 solo launches vs the
+    fragmented path; knob tuner; batch == solo == oracle for every query."""
+    import concurrent.futures as cf
+
+    import torch
+    import oracle
+    from paper_2605_10511_amd import dpf, tune
+
+    M, tables, encs = mix_tables(args.scale)
+    ctx = dpf.Context(0)
+    db = dpf.Database(ctx)
+    t0 = time.time()
+    for name, cols in tables.items():
+        db.add_table(name, cols, encs.get(name), placement="HBM")
+    log(f"[mix] {len(tables)} tables encoded + uploaded in {time.time() - t0:.1f} s")
+    specs = [q[2] for q in M["queries"]]
+    plans = [db.plan(sp) for sp in specs]
+    torch.cuda.synchronize()
+    rows = [db.tables[sp["fact"]][referenced_columns(sp)[0]].info().nrows for sp in specs]
+    alg = [sum(db.tables[sp["fact"]][c].info().compressed_bytes for c in referenced_columns(sp)) for sp in specs]
+    tot_rows, tot_bytes = sum(rows), sum(alg)
+    log(f"[mix] {len(plans)} plans: {tot_rows:,} query rows, {tot_bytes / 1e9:.3f} GB compressed")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        out = [fn() for _ in range(reps)]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - w0) * 1e3 / reps, out[-1]
+
+    best = {}
+    tuned = None
+    if not args.no_tune:
+        tuned = tune.tune(ctx, plans, refresh=True, log=log)
+        best = dict(tuned["best"])
+        log(f"[mix] tuner best {best}: {tuned['ms']:.3f} ms")
+
+    def batch():
+        return dpf.execute(ctx, plans, **best)
+
+    def batch_default():
+        return dpf.execute(ctx, plans)
+
+    def solo():  # each query alone, default knobs (the batch's knobs starve a lone query)
+        return [dpf.execute(ctx, [p]) for p in plans]
+
+    def frag():
+        return [dpf.execute(ctx, [p], mode="FRAGMENTED") for p in plans]
+
+    l0 = ctx.info().launches
+    bms, bwall, bres = timed(batch, args.steps)
+    blaunch = (ctx.info().launches - l0) / (args.steps + 1)
+    dms, _, dres = timed(batch_default, args.steps)
+    dres.release()
+    sms, swall, sres = timed(solo, max(1, args.steps // 4))
+    fms, fwall, fres = timed(frag, 1)
+    got_b = [bres.get(i) for i in range(len(plans))]
+    got_s = [r.get(0) for r in sres]
+    got_f = [r.get(0) for r in fres]
+    bres.release()
+    for r in sres + fres:
+        r.release()
+    batch_eq_solo = all(np.array_equal(a, b) for a, b in zip(got_b, got_s))
+    frag_eq = all(np.array_equal(a, b) for a, b in zip(got_b, got_f))
+    log(f"[mix] batch {bms:.3f} ms ({blaunch:.0f} launch; default knobs {dms:.3f} ms), solo {sms:.3f} ms, "
+        f"fragmented {fms:.3f} ms; "
+        f"batch==solo {batch_eq_solo}, fragmented==batch {frag_eq}")
+
+    cpu = None
+    parity = None
+    if not args.no_oracle:
+        t2 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            want = list(ex.map(lambda sp: oracle.run(sp, tables), specs))
+        ot = time.perf_counter() - t2
+        parity = all(np.array_equal(w, g) for w, g in zip(want, got_b))
+        cpu = {"value": tot_rows / ot, "unit": "rows/s", "cores": min(16, os.cpu_count() or 1),
+               "kind": "oracle", "sample": f"all 64 queries of the mix ({tot_rows:,} query rows), one "
+                                           f"oracle call per query on a thread pool ({ot:.1f} s)"}
+        log(f"[mix] oracle {ot:.1f} s; batch result {'==' if parity else '!='} oracle")
+
+    achieved = tot_bytes / (bms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": tot_rows / (bwall * 1e-3),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": bwall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "batched mix: 64 queries (filter-aggregate / star-join, 50/50) over a pool of "
+                               "4 + 4 fact tables of log-uniform size in [1M, 120M] rows, one fused launch",
+                   "query_rows": tot_rows, "compressed_bytes": tot_bytes, "knobs": best},
+        "compressed_gbps": tot_bytes / (bwall * 1e-3) / 1e9,
+        "launches_per_batch": blaunch,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": "fused_kernel",
+                     "kernel_ms": bms},
+        "batch_default_knobs_ms": dms,
+        "solo": {"ms": sms, "launches": len(plans), "speedup_of_batch": sms / bms, "knobs": "default"},
+        "fragmented": {"ms": fms, "speedup_of_batch": fms / bms, "matches_batch": frag_eq},
+        "batch_equals_solo": batch_eq_solo,
+        "tuner": tuned,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Config 5: serve Poisson request streams against a resident fact table
+    (and, optionally, a host-mapped one); one JSON line."""
+    import concurrent.futures as cf
+
+    import torch
+
+    import oracle
+    from datagen import workloads as W
+    from paper_2605_10511_amd import dpf
+    from paper_2605_10511_amd.serve import Request, Server, latency_stats
+
+    rates = [float(x) for x in str(args.qps).split(",") if x]
+    dims = W.sj_dims(seed=3)
+    ctx = dpf.Context(0)
+    db = dpf.Database(ctx)
+    t0 = time.time()
+    for name, cols in dims.items():
+        db.add_table(name, cols)
+    res = W.union_table(args.resident_rows, seed=5, dims=dims)
+    db.add_table("res", res, W.FA_ENCODINGS, placement="HBM")
+    res_bytes = sum(c.info().compressed_bytes for c in db.tables["res"].values())
+    log(f"[serve] resident table {args.resident_rows:,} rows, {res_bytes / 1e9:.2f} GB compressed, "
+        f"built in {time.time() - t0:.1f} s")
+    host = None
+    if args.host_rows > 0:
+        t1 = time.time()
+        host = W.union_table(args.host_rows, seed=55, dims=dims)
+        db.add_table("host", host, W.FA_ENCODINGS, placement="HOST_MAPPED")
+        host_bytes = sum(c.info().compressed_bytes for c in db.tables["host"].values())
+        log(f"[serve] host-mapped table {args.host_rows:,} rows, {host_bytes / 1e9:.2f} GB, "
+            f"built in {time.time() - t1:.1f} s")
+        del host  # the pinned copy is the table now
+
+    def alg_bytes(spec):
+        t = db.tables[spec["fact"]]
+        used = [p["col"] for p in spec.get("filters", [])] + [p["fk"] for p in spec.get("probes", [])]
+        used += [r["col"] for r in spec.get("group_by", []) if "col" in r]
+        used += [tm["ref"]["col"] for a in spec["aggs"] for tm in a.get("terms", [])
+                 if "ref" in tm and "col" in tm["ref"]]
+        return sum(t[c].info().compressed_bytes for c in dict.fromkeys(used))
+
+    srv = Server(ctx, db, nstreams=4, slots=8, state_budget=4 << 30)
+    # warm: one request of each template
+    warm = [Request(0.0, "FA", W.fa_query("res"), "res"),
+            Request(0.0, "SJ", W.sj_query("res"), "res")]
+    srv.run(warm)
+    per_rate = []
+    sample = []
+    for lam in rates:
+        gen = W.serve_requests(5, lam, args.seconds, "res")
+        reqs = [Request(t, tmpl, spec, "res") for t, tmpl, spec in gen]
+        if host is not None or args.host_rows > 0:
+            for t, tmpl, spec in W.serve_requests(55, 1.0, args.seconds, "host", stream="hostreq"):
+                reqs.append(Request(t, tmpl, spec, "host"))
+        log(f"[serve] lambda {lam:g}: {len(reqs)} requests over {args.seconds:g} s")
+        t1 = time.perf_counter()
+        done = srv.run(reqs, t_limit=args.seconds * 3)
+        wall = time.perf_counter() - t1
+        span = max([r.done for r in done], default=args.seconds)
+        st_res = latency_stats([r for r in done if r.table == "res"], span)
+        st_host = latency_stats([r for r in done if r.table == "host"], span)
+        moved = sum(alg_bytes(r.spec) for r in done if r.table == "res")
+        hmoved = sum(alg_bytes(r.spec) for r in done if r.table == "host")
+        row = {"lambda_qps": lam, "offered": len(reqs), "wall_s": wall, "resident": st_res,
+               "hbm_gbps": moved / span / 1e9, "host_mapped": st_host if args.host_rows > 0 else None,
+               "host_link_gbps": hmoved / span / 1e9 if args.host_rows > 0 else None}
+        per_rate.append(row)
+        log(f"[serve] lambda {lam:g}: {st_res['completed']} done, {st_res['qps']:.1f} QPS, "
+            f"p50 {st_res.get('p50_ms', 0):.2f} ms, p99 {st_res.get('p99_ms', 0):.2f} ms, "
+            f"{row['hbm_gbps']:.0f} GB/s")
+        if not sample:
+            fa = [r for r in done if r.table == "res" and r.template == "FA"][:8]
+            sj = [r for r in done if r.table == "res" and r.template == "SJ"][:8]
+            sample = fa + sj
+
+    # alone-vs-mix: each sampled request again, alone, must give the same rows
+    alone_eq = True
+    for r in sample:
+        hashes = [srv._hash(pr) for pr in r.spec.get("probes", [])]
+        p = db.plan(r.spec, hashes=hashes)
+        out = dpf.execute(ctx, [p])
+        torch.cuda.synchronize()
+        alone_eq &= bool(np.array_equal(out.get(0), r.rows))
+        out.release()
+        p.release()
+    log(f"[serve] alone == served for {len(sample)} sampled requests: {alone_eq}")
+
+    cpu = None
+    parity = None
+    if not args.no_oracle and sample:
+        chk = [sample[0], sample[len(sample) // 2]]
+        tables = {"res": res, **dims}
+        t2 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=2) as ex:
+            want = list(ex.map(lambda r: oracle.run(r.spec, tables), chk))
+        ot = time.perf_counter() - t2
+        parity = all(np.array_equal(w, r.rows) for w, r in zip(want, chk))
+        nrows = args.resident_rows * len(chk)
+        cpu = {"value": nrows / ot, "unit": "rows/s", "cores": 2, "kind": "oracle",
+               "sample": f"two served requests (one FA, one SJ) re-evaluated on the "
+                         f"{args.resident_rows:,}-row resident table, one thread each ({ot:.1f} s)"}
+        log(f"[serve] oracle on 2 requests {ot:.1f} s: {'==' if parity else '!='}")
+    srv.close()
+
+    top = per_rate[-1]["resident"] if per_rate else {}
+    out = {
+        "metric": METRIC,
+        "value": top.get("p99_ms"),
+        "unit": "ms (p99, resident table, highest offered rate)",
+        "n_gpus": 1,
+        "steps": len(rates),
+        "warmup": 1,
+        "ms_per_step": top.get("p50_ms"),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {rates} QPS for {args.seconds:g} s each, "
+                               f"FA/SJ templates on a {args.resident_rows:,}-row resident union table"
+                               + (f" plus 1 QPS on a {args.host_rows:,}-row host-mapped table"
+                                  if args.host_rows > 0 else ""),
+                   "streams": 4, "slots": 8, "state_budget_bytes": 4 << 30,
+                   "resident_compressed_bytes": res_bytes},
+        "rates": per_rate,
+        "hash_builds": srv.hash_builds,
+        "alone_equals_served": alone_eq,
+        "roofline": {"bound": "hbm", "achieved": per_rate[-1]["hbm_gbps"] if per_rate else None,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": (per_rate[-1]["hbm_gbps"] / HBM_PEAK_GBPS) if per_rate else None,
+                     "traffic": None, "kernel": "fused_kernel"},
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
     }

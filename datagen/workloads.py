@@ -278,6 +278,51 @@ def mix_plan(seed: int = 4, nq: int = 64, min_rows: int = 1_000_000, max_rows: i
     return {"fa_sizes": fa_sizes, "sj_sizes": sj_sizes, "queries": queries}
 
 
-__all__ = ["Strings", "fa_table", "fa_query", "wide_table", "wide_query", "wide_words",
+# ----------------------------------------------------------------------------
+# Serving: a union-schema fact table and Poisson request streams
+# ----------------------------------------------------------------------------
+def union_table(n: int, seed: int = 5, dims: dict | None = None) -> dict:
+    """The filter-aggregate columns and the star-join foreign keys and revenue
+    in one fact table of n rows (both query templates run on it)."""
+    t = fa_table(n, seed=seed)
+    t.update(sj_fact(n, seed=seed, dims=dims, name="u"))
+    return t
+
+
+def serve_requests(seed: int, qps: float, seconds: float, table: str, stream: str = "req") -> list:
+    """Poisson arrivals at ``qps`` for ``seconds``: [(arrival_s, template,
+    spec)], exponential gaps and template constants from one seeded stream
+    (template FA or SJ with probability 1/2, constants uniform over each
+    attribute's domain)."""
+    n = max(16, int(qps * seconds * 1.5) + 64)
+    u = (raw(seed, f"{stream}@{qps:g}", 8 * n).astype(np.float64) + 0.5) / 2.0**64
+    k = 0
+
+    def nxt():
+        nonlocal k
+        k += 1
+        return float(u[k - 1])
+
+    out = []
+    t = 0.0
+    while True:
+        t += -math.log(nxt()) / qps
+        if t >= seconds:
+            break
+        if nxt() < 0.5:
+            c = min(int(nxt() * 9), 8)
+            spec = fa_query(table, date_lt=min(int(nxt() * NDATES), NDATES - 1), disc_lo=c, disc_hi=c + 2,
+                            qty_lt=2 + min(int(nxt() * 50), 49))
+            out.append((t, "FA", spec))
+        else:
+            spec = sj_query(table, part_attr=min(int(nxt() * 1000), 999), supp_nation=min(int(nxt() * 25), 24),
+                            date_dow=min(int(nxt() * 7), 6), cust_region=min(int(nxt() * 5), 4))
+            out.append((t, "SJ", spec))
+        if k + 8 > len(u):
+            break
+    return out
+
+
+__all__ = ["Strings", "union_table", "serve_requests", "fa_table", "fa_query", "wide_table", "wide_query", "wide_words",
            "sj_dims", "sj_fact", "sj_query", "mix_plan", "FA_ENCODINGS", "WIDE_ENCODINGS",
            "FLAG_A_VALUES", "FLAG_B_VALUES", "NDATES"]

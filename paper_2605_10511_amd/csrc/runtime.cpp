@@ -661,7 +661,7 @@ namespace {
 constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
-constexpr int kTargetWavesPerCU = 20;  // resident waves per CU the default launch aims for
+constexpr int kTargetWavesPerCU = 16;  // the fused kernel's register budget allows 4 waves per SIMD
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
 // shared area within budget; fills lds offsets and lds_shared.
@@ -1041,7 +1041,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
             int32_t want = o.lds_hash_bytes < 0 ? kDefaultLdsHash : o.lds_hash_bytes;
             if (p->lds_budget != want) {
                 assign_lds(p, want);
-                HIP_TRY(hipMemcpy(p->dq, &p->hq, sizeof(DevQuery), hipMemcpyHostToDevice));
+                HIP_TRY(hipMemcpyAsync(p->dq, &p->hq, sizeof(DevQuery), hipMemcpyHostToDevice, s));
             }
         }
         BatchArgs a;

@@ -425,6 +425,8 @@ class Plan:
         _check(lib.dpf_plan_build(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
         self.ctx = ctx
+        self.ncols = len(names)
+        self.nrows = fact[names[0]].info().nrows
 
     @staticmethod
     def _ref(r: dict, index: dict) -> dpf_ref:

@@ -1,0 +1,186 @@
+"""Serving loop over the fused query path.
+
+Requests arrive over time (Poisson in the benchmark).  The server
+
+* prepares each request on arrival: dimension hash tables come from a cache
+  keyed by (dimension, key, filter, payloads) and are built once, on the
+  device (paper Section 3.1, Kernel #1); the plan is compiled against the
+  resident fact columns;
+* admits prepared requests while their device state (plan workspace plus
+  the hash tables they hold, ``dpf_plan_footprint``) fits the state budget
+  and an in-flight slot is free;
+* batches whatever is admitted into ONE fused launch per free stream
+  (continuous batching: a new batch starts as soon as a stream drains, it
+  does not wait for a full batch), so queries that arrive together share a
+  launch and the work queue of one persistent kernel (Section 3.2);
+* completes a batch when its stream event fires, decodes the records and
+  records arrival-to-result latency.
+
+Tables larger than the residency budget are placed in pinned host memory
+mapped into the device and scanned over the host link (Section 3.1's zero
+copy path), on a stream of their own.
+"""
+from __future__ import annotations
+
+import collections
+import json
+import time
+
+import numpy as np
+
+from . import dpf
+
+
+class Request:
+    __slots__ = ("t", "template", "spec", "plan", "footprint", "rows", "done", "issued", "table")
+
+    def __init__(self, t: float, template: str, spec: dict, table: str):
+        self.t = t
+        self.template = template
+        self.spec = spec
+        self.table = table
+        self.plan = None
+        self.footprint = 0
+        self.rows = None
+        self.done = None
+        self.issued = None
+
+
+class _Batch:
+    __slots__ = ("stream", "event", "reqs", "result", "footprint")
+
+
+class Server:
+    def __init__(self, ctx: dpf.Context, db: dpf.Database, nstreams: int = 4, slots: int = 8,
+                 state_budget: int = 4 << 30, placements: dict | None = None):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.db = db
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]  # default priority
+        self.slots = slots
+        self.state_budget = state_budget
+        self.hashes: dict[str, dpf.Hash] = {}
+        self.placements = placements or {}
+        self.hash_builds = 0
+
+    # -- preparation -------------------------------------------------------
+    def _hash(self, pr: dict) -> dpf.Hash:
+        key = json.dumps([pr["dim"], pr["key"], pr.get("filters", []), pr.get("payloads", [])], sort_keys=True)
+        h = self.hashes.get(key)
+        if h is None:
+            cols = self.db.tables[pr["dim"]]
+            used = [pr["key"]] + [p["col"] for p in pr.get("filters", [])] + list(pr.get("payloads", []))
+            sub = {c: cols[c] for c in dict.fromkeys(used)}
+            s = self.streams[0]
+            h = dpf.Hash(self.ctx, sub, pr["key"], pr.get("filters", []), pr.get("payloads", []),
+                         self.placements.get(pr["dim"], "AUTO"), s)
+            s.synchronize()  # later batches on other streams read it
+            self.hashes[key] = h
+            self.hash_builds += 1
+        return h
+
+    def prepare(self, r: Request):
+        hashes = [self._hash(pr) for pr in r.spec.get("probes", [])]
+        r.plan = self.db.plan(r.spec, hashes=hashes)
+        r.footprint = r.plan.footprint()
+
+    # -- the loop ----------------------------------------------------------
+    def run(self, reqs: list, log=None, t_limit: float | None = None) -> list:
+        """Serve ``reqs`` (ascending arrival times, seconds from the start);
+        returns the completed requests with ``done`` and ``rows`` set."""
+        torch = self.torch
+        reqs = sorted(reqs, key=lambda r: r.t)
+        ready = collections.deque()
+        inflight: list[_Batch] = []
+        free = list(range(len(self.streams)))
+        used = 0
+        nin = 0
+        done = []
+        i = 0
+        t0 = time.perf_counter()
+        while i < len(reqs) or ready or inflight:
+            now = time.perf_counter() - t0
+            if t_limit is not None and now > t_limit and not inflight:
+                break
+            progressed = False
+            # arrivals: prepare in arrival order
+            while i < len(reqs) and reqs[i].t <= now:
+                self.prepare(reqs[i])
+                ready.append(reqs[i])
+                i += 1
+                progressed = True
+            # completions
+            for b in list(inflight):
+                if b.event.query():
+                    t = time.perf_counter() - t0
+                    for k, r in enumerate(b.reqs):
+                        r.rows = b.result.get(k)
+                        r.done = t
+                        r.plan.release()
+                        r.plan = None
+                    b.result.release()
+                    used -= b.footprint
+                    nin -= len(b.reqs)
+                    free.append(b.stream)
+                    inflight.remove(b)
+                    done.extend(b.reqs)
+                    progressed = True
+            # admission + launch: one fused batch per free stream
+            while free and ready and nin < self.slots:
+                batch = []
+                fp = 0
+                while ready and nin + len(batch) < self.slots and len(batch) < 64:
+                    r = ready[0]
+                    if used + fp + r.footprint > self.state_budget and (batch or inflight):
+                        break  # wait for state to drain
+                    batch.append(ready.popleft())
+                    fp += r.footprint
+                if not batch:
+                    break
+                si = free.pop(0)
+                s = self.streams[si]
+                b = _Batch()
+                b.stream = si
+                b.reqs = batch
+                b.footprint = fp
+                issued = time.perf_counter() - t0
+                for r in batch:
+                    r.issued = issued
+                b.result = dpf.execute(self.ctx, [r.plan for r in batch], stream=s)
+                b.event = torch.cuda.Event()
+                b.event.record(s)
+                inflight.append(b)
+                used += fp
+                nin += len(batch)
+                progressed = True
+            if not progressed:
+                nxt = reqs[i].t - (time.perf_counter() - t0) if i < len(reqs) else 0.0
+                if not inflight and nxt > 0:
+                    time.sleep(min(nxt, 0.002))
+                else:
+                    time.sleep(20e-6)
+        for r in ready:
+            if r.plan is not None:
+                r.plan.release()
+                r.plan = None
+        return done
+
+    def close(self):
+        for h in self.hashes.values():
+            h.release()
+        self.hashes.clear()
+
+
+def latency_stats(done: list, seconds: float) -> dict:
+    lat = np.array([(r.done - r.t) * 1e3 for r in done]) if done else np.zeros(0)
+    out = {"completed": len(done), "qps": len(done) / seconds if seconds > 0 else 0.0}
+    if len(lat):
+        out.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "mean_ms": float(lat.mean()), "max_ms": float(lat.max())})
+    for tmpl in ("FA", "SJ"):
+        sel = np.array([(r.done - r.t) * 1e3 for r in done if r.template == tmpl])
+        if len(sel):
+            out[tmpl] = {"n": int(len(sel)), "p50_ms": float(np.percentile(sel, 50)),
+                         "p99_ms": float(np.percentile(sel, 99))}
+    return out

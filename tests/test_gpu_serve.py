@@ -1,0 +1,85 @@
+"""GPU: the launch-knob tuner and the serving loop.  Served results must equal
+the oracle's and a lone execution's, whatever batch they shared."""
+import numpy as np
+import pytest
+
+import oracle
+from datagen import workloads as W
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2605_10511_amd import dpf
+    assert torch.cuda.is_available()
+    ctx = dpf.Context(0)
+    dims = W.sj_dims(seed=3, scale=0.01)
+    res = W.union_table(300_000, seed=5, dims=dims)
+    tables = {"res": res, **dims}
+    db = G.make_db(ctx, tables, {"res": W.FA_ENCODINGS})
+    return ctx, db, tables
+
+
+def test_tuner_picks_a_measured_point(env, tmp_path):
+    from paper_2605_10511_amd import dpf, tune
+    ctx, db, tables = env
+    specs = [W.fa_query("res"), W.sj_query("res", part_attr=3)]
+    plans = [db.plan(s) for s in specs]
+    grid = {"rows_per_item": [16384, 65536], "wg_per_cu": [1, 2], "lds_hash_bytes": [0, 32768]}
+    cache = str(tmp_path / "tune.json")
+    G.say("tuner: 8 points")
+    e = tune.tune(ctx, plans, grid=grid, reps=2, cache=cache)
+    ok = [t for t in e["table"] if t["ms"] is not None]
+    assert ok and e["ms"] == min(t["ms"] for t in ok)
+    again = tune.tune(ctx, plans, grid=grid, cache=cache)
+    assert again["best"] == e["best"] and again["key"] == e["key"]
+    import torch
+    r1 = dpf.execute(ctx, plans, **e["best"])
+    r2 = dpf.execute(ctx, plans)
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        G.assert_same(r1.get(i), oracle.run(s, tables), f"tuned plan {i}")
+        G.assert_same(r2.get(i), r1.get(i), f"default plan {i}")
+    r1.release()
+    r2.release()
+    for p in plans:
+        p.release()
+
+
+def test_served_results_equal_oracle_and_alone(env):
+    import torch
+    from paper_2605_10511_amd import dpf, serve
+    ctx, db, tables = env
+    gen = W.serve_requests(11, 400.0, 0.1, "res")
+    reqs = [serve.Request(t, k, s, "res") for t, k, s in gen]
+    G.say(f"serving {len(reqs)} requests")
+    srv = serve.Server(ctx, db, nstreams=4, slots=8, state_budget=1 << 30)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert all(r.done >= r.t for r in done)
+    for r in done:
+        G.assert_same(r.rows, oracle.run(r.spec, tables), f"served {r.template} at {r.t:.4f}")
+    for r in done[:6]:
+        p = db.plan(r.spec, hashes=[srv._hash(pr) for pr in r.spec.get("probes", [])])
+        out = dpf.execute(ctx, [p])
+        torch.cuda.synchronize()
+        G.assert_same(out.get(0), r.rows, "alone vs served")
+        out.release()
+        p.release()
+    srv.close()
+
+
+def test_state_budget_serialises_batches(env):
+    from paper_2605_10511_amd import serve
+    ctx, db, tables = env
+    gen = W.serve_requests(12, 1000.0, 0.02, "res")
+    reqs = [serve.Request(t, k, s, "res") for t, k, s in gen]
+    srv = serve.Server(ctx, db, nstreams=2, slots=8, state_budget=1)  # one request at a time
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    for r in done:
+        G.assert_same(r.rows, oracle.run(r.spec, tables), "budget-limited")
+    srv.close()
