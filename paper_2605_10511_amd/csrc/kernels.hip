@@ -588,6 +588,40 @@ __device__ __forceinline__ int hash_find(CH& h, const uint8_t* smem_shared, int6
     return -1;
 }
 
+// Membership of the lane's four keys (mask bit k: row 64 k + lane is live),
+// probed in lockstep so that the four chains' loads are in flight together.
+template <bool kLds>
+__device__ __forceinline__ uint32_t hash_member4(CH& h, const uint8_t* smem_shared, const int64_t key[4],
+                                                 uint32_t live) {
+    const int32_t* lkeys = reinterpret_cast<const int32_t*>(smem_shared + h.lds_off);
+    cptr<int32_t> gkeys = ro(h.keys);
+    uint32_t slot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (key[k] < INT32_MIN || key[k] > INT32_MAX || key[k] == kEmptyKey) live &= ~(1u << k);
+        slot[k] = hash32((int32_t)key[k], h.log2cap);
+    }
+    uint32_t found = 0;
+    for (uint32_t n = 0; n <= h.cap_mask && __ballot(live != 0); ++n) {
+        int32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = (live >> k) & 1u ? (kLds ? lkeys[slot[k]] : gkeys[slot[k]]) : kEmptyKey;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!((live >> k) & 1u)) continue;
+            if (x[k] == (int32_t)key[k]) {
+                found |= 1u << k;
+                live &= ~(1u << k);
+            } else if (x[k] == kEmptyKey) {
+                live &= ~(1u << k);
+            } else {
+                slot[k] = (slot[k] + 1) & h.cap_mask;
+            }
+        }
+    }
+    return found;
+}
+
 template <bool kLds>
 __device__ __forceinline__ int64_t hash_payload(CH& h, const uint8_t* smem_shared, int k,
                                                 int slot) {
@@ -752,8 +786,9 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
     const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
     const int npreds = Q.npreds;
 
-    if (npreds == 0) {
-        // No fact predicate: every valid row goes straight to stage B.
+    if (npreds == 0 && Q.nprobes == 0) {
+        // Neither a fact predicate nor a join: every valid row goes straight
+        // to stage B.
         for (int k = 0; k < 4; ++k) {
             if (64 * k >= nvalid) break;
             int i = 64 * k + lane;
@@ -761,10 +796,28 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
         }
         return;
     }
-
-    const uint32_t mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
-                              ? filter_tile<true>(Q, W, m, lane, nvalid, ok_hdr)
-                              : filter_tile<false>(Q, W, m, lane, nvalid, ok_hdr);
+    uint32_t mask;
+    if (npreds == 0) {
+        // No fact predicate: the first (most selective) probe filters as a
+        // semi-join over the dense foreign keys; its survivors are probed
+        // again, with payloads, in stage B.
+        mask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
+        CPR& P0 = Q.probes[0];
+        CC& fc = Q.cols[P0.fk_col];
+        int64_t fk[4];
+        ok_hdr &= decode_dense(fc, m, lane, fk);
+        if (fc.enc == ENC_DICT)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
+        mask = P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
+                                 : hash_member4<false>(P0.h, smem_shared, fk, mask);
+    } else {
+        mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
+                   ? filter_tile<true>(Q, W, m, lane, nvalid, ok_hdr)
+                   : filter_tile<false>(Q, W, m, lane, nvalid, ok_hdr);
+    }
     if (__ballot(mask != 0) == 0) return;
 
     // Queue survivors (wave ballot + mbcnt compaction).

@@ -661,6 +661,7 @@ namespace {
 constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
+constexpr int64_t kDefaultMbPerItem = 64;  // 16,384 rows
 constexpr int kTargetWavesPerCU = 16;  // the fused kernel's register budget allows 4 waves per SIMD
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
@@ -1032,8 +1033,8 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         }
     } else if (o.mode == DPF_MODE_FUSED) {
         if (n > kMaxBatch) return fail(DPF_ERR_UNSUPPORTED, "at most 64 plans per fused launch");
-        int rows_per_item = o.rows_per_item ? o.rows_per_item : 16384;
-        if (rows_per_item < kMB || rows_per_item % kMB) return fail(DPF_ERR_INVALID_ARG, "rows_per_item: multiple of 256");
+        if (o.rows_per_item && (o.rows_per_item < kMB || o.rows_per_item % kMB))
+            return fail(DPF_ERR_INVALID_ARG, "rows_per_item: multiple of 256");
         // LDS placement follows the requested budget (re-uploads the
         // descriptor only when the budget changes)
         for (int i = 0; i < n; ++i) {
@@ -1047,21 +1048,18 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         BatchArgs a;
         std::memset(&a, 0, sizeof a);
         a.nq = n;
-        a.mb_per_item = rows_per_item / kMB;
         a.counters = plans[0]->counters;
-        int32_t items = 0;
         bool str = false, pend = false;
         int32_t shared = 0;
+        int64_t total_mb = 0;
         for (int i = 0; i < n; ++i) {
             const DevQuery& q = plans[i]->hq;
             a.q[i] = plans[i]->dq;
-            a.item_start[i] = items;
-            items += (q.nmb + a.mb_per_item - 1) / a.mb_per_item;
             str |= q.has_str != 0;
-            pend |= q.npreds > 0;
+            pend |= q.npreds > 0 || q.nprobes > 0;
             shared = std::max(shared, q.lds_shared);
+            total_mb += q.nmb;
         }
-        a.item_start[n] = items;
         a.lds_shared = (int32_t)align_up((size_t)shared, 16);
         a.str_stage = str;
         a.pend_stage = pend;
@@ -1084,6 +1082,22 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         if (wg <= 0) wg = std::max(1, kTargetWavesPerCU / waves);
         wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
         const int grid = std::max(1, ctx->ncu * wg);
+        // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
+        // shrunk for small batches so that every workgroup gets about four
+        // items, but never below one mini block per wave.
+        int64_t mb_per_item = o.rows_per_item / kMB;
+        if (mb_per_item == 0) {
+            mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 4LL * grid - 1) / (4LL * grid));
+            mb_per_item = std::max<int64_t>(mb_per_item, waves);
+        }
+        a.mb_per_item = (int32_t)mb_per_item;
+        int64_t items = 0;
+        for (int i = 0; i < n; ++i) {
+            a.item_start[i] = (int32_t)items;
+            items += (plans[i]->hq.nmb + mb_per_item - 1) / mb_per_item;
+        }
+        if (items > INT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "too many work items; raise rows_per_item");
+        a.item_start[n] = (int32_t)items;
         HIP_TRY(launch_fused(a, waves, grid, lds, s));
         ctx->launches++;
     } else {
