@@ -27,6 +27,9 @@ constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
 constexpr int64_t kMaxGroups = int64_t(1) << 22;  // direct-indexed group table limit
 constexpr int kStrHeapCap = 11264;  // per-wave LDS bytes staging one mini block's strings
 constexpr int32_t kEmptyKey = INT32_MIN;
+constexpr int kXcds = 8;             // XCDs per device; workgroup i is dispatched to XCD i % 8
+constexpr int kCounterStride = 32;   // 32-bit words between work-queue counters (128-byte lines)
+constexpr int kCounterWords = (2 * kXcds + 1) * kCounterStride;
 
 enum : int32_t { ENC_FOR = 1, ENC_DELTA = 2, ENC_DICT = 3, ENC_VARLEN = 4 };
 
@@ -121,7 +124,8 @@ struct BatchArgs {
     int32_t item_start[kMaxBatch + 1];
     int32_t nq;
     int32_t mb_per_item;
-    uint32_t* counters;   // [0] work-queue head, [1] finished workgroups
+    uint32_t* counters;   // kCounterWords: per XCD x, the claim head of item range x (line x) and
+                          // its finished workgroups (line 8 + x); finished XCDs (line 16)
     int32_t lds_shared;   // max lds_shared over the batch
     int32_t str_stage;    // per-wave string staging present
     int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate)

@@ -209,6 +209,38 @@ __device__ __forceinline__ int64_t dict_value(CC& c, int64_t code, bool& ok) {
 }
 
 // ---------------------------------------------------------------------------
+// Zone test from the mini-block header alone.  A FOR mini block holds values
+// in [base, base + 2^b - 1]; a DELTA one, anchor + i * dmin + (a sum of i
+// packed differences in [0, 2^b - 1]) for i < 256.  When that interval lies
+// inside a range atom every row passes, when it misses the atom none does,
+// and the column need not be decoded (the paper's zone maps, Section 3.4,
+// at mini-block granularity and with no bytes beyond the header).
+// Returns 1: all rows pass, 0: none, -1: undecided.  Wave-uniform (scalar).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int zone_test(CC& c, CP& p, int m) {
+    if (p.kind != PK_RANGE && p.kind != PK_NE) return -1;
+    const MbHdr h = mb_hdr(c, m);
+    if (!h.ok || h.b > 40) return -1;
+    const __int128 span = (h.b ? (((__int128)1) << h.b) - 1 : 0);
+    __int128 lo = h.base, hi = h.base;
+    if (c.enc == ENC_DELTA) {
+        const __int128 d = (__int128)ro(c.dmin)[m] * (kMB - 1);
+        if (d < 0) lo += d; else hi += d;
+        hi += span * (kMB - 1);
+    } else {
+        hi += span;
+    }
+    if (p.kind == PK_RANGE) {
+        if (lo >= p.lo && hi <= p.hi) return 1;
+        if (hi < p.lo || lo > p.hi) return 0;
+        return -1;
+    }
+    if (hi < p.lo || lo > p.lo) return 1;  // NE: the excluded value is outside
+    if (lo == hi) return 0;                // every row equals it
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
 // Integer predicates on four dense values -> 4-bit mask
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t eval_int_pred(CP& p, cptr<int64_t> in_vals,
@@ -476,6 +508,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
         uint32_t hits = 0;
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
+            if (base + (uint32_t)it * kWave > nvec) break;  // slots past the mini block hold zeros
             const uint4 w = S.W[it];
             uint32_t nx, nx2;
             next_words(S, it, lane, nx, nx2);
@@ -765,6 +798,9 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
             if (P.n1 >= 4 && P.n2 >= 4) mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
             else mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
         } else {
+            const int z = zone_test(Q.cols[P.col], P, m);
+            if (z == 1) continue;
+            if (z == 0) return 0;
             if (P.col != last_col) {
                 ok_hdr &= decode_dense(Q.cols[P.col], m, lane, v);
                 last_col = P.col;
@@ -853,16 +889,20 @@ __device__ __forceinline__ WaveArea wave_area(uint8_t* p, bool pend_stage) {
     return W;
 }
 
-// Merge the workgroup's LDS group table into the plan's global table.
-__device__ void flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
-    if (!Q.agg_lds) return;
+// Merge the workgroup's LDS group table into the plan's global table.  The
+// device-scope adds return their old values, which the caller folds into a
+// sink: once the sink is known the adds have been performed.
+__device__ unsigned long long flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
+    if (!Q.agg_lds) return 0;
     const int64_t n = Q.ngroups * Q.nacc;
     unsigned long long* T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off);
+    unsigned long long sink = 0;
     for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
         unsigned long long x = T[e];
-        if (x) atomicAdd(reinterpret_cast<unsigned long long*>(Q.agg) + e, x);
+        if (x) sink += atomicAdd(reinterpret_cast<unsigned long long*>(Q.agg) + e, x);
         T[e] = 0;
     }
+    return sink;
 }
 
 // Load a plan's LDS-resident dimension tables and clear its LDS group table.
@@ -918,6 +958,44 @@ __device__ void emit_records(CQ& Q, int32_t* ctrl) {
 }
 
 // ---------------------------------------------------------------------------
+// Work queue.  Workgroup i runs on XCD i % 8 (round-robin dispatch), and each
+// XCD has its own L2, so a single queue head would serialise every claim of
+// the grid on one device-coherent atomic.  Instead the items are split into
+// eight contiguous ranges with one head each: a workgroup claims from its
+// XCD's range, then steals from the others, skipping a drained range after a
+// plain load of its head.  Completion counts per XCD and then across XCDs.
+// The dispatch rule only affects speed: any workgroup may take any item.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t* ctr(const BatchArgs& a, int i) { return a.counters + i * kCounterStride; }
+
+__device__ __forceinline__ int claim_item(const BatchArgs& a, int home, uint32_t& drained, int total) {
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (home + k) & (kXcds - 1);
+        if ((drained >> x) & 1u) continue;
+        const uint32_t lo = (uint32_t)((int64_t)total * x / kXcds);
+        const uint32_t n = (uint32_t)((int64_t)total * (x + 1) / kXcds) - lo;
+        uint32_t* head = ctr(a, x);
+        if (k > 0 && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) {
+            drained |= 1u << x;
+            continue;
+        }
+        const uint32_t j = atomicAdd(head, 1u);
+        if (j < n) return (int)(lo + j);
+        drained |= 1u << x;
+    }
+    return -1;
+}
+
+// True for the workgroup that finishes last (call after a fence).
+__device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
+    const uint32_t nhome = (gridDim.x - 1u - (uint32_t)home) / kXcds + 1u;  // workgroups homed on this XCD
+    if (atomicAdd(ctr(a, kXcds + home), 1u) != nhome - 1u) return false;
+    __threadfence();
+    const uint32_t nx = gridDim.x < (uint32_t)kXcds ? gridDim.x : (uint32_t)kXcds;
+    return atomicAdd(ctr(a, 2 * kXcds), 1u) == nx - 1u;
+}
+
+// ---------------------------------------------------------------------------
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
 template <int NW>
@@ -933,15 +1011,19 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         wave_area(smem + 64 + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage, pend_stage), pend_stage);
     const int total_items = a.item_start[a.nq];
 
+    const int home = (int)(blockIdx.x % kXcds);
+    uint32_t drained = 0;  // thread 0: item ranges found empty
+    unsigned long long sink = 0;  // old values of this thread's device-scope atomics
+    bool direct = false;          // some plan aggregated straight into global memory
     int cur = -1;
     bool ok_hdr = true;
     int npend = 0;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(&a.counters[0], 1u);
+        if (threadIdx.x == 0) ctrl[0] = claim_item(a, home, drained, total_items);
         __syncthreads();
         const int item = uniform_i32(ctrl[0]);
-        if (item >= total_items) break;
+        if (item < 0) break;
         int qi = 0;
         while (qi + 1 < a.nq && a.item_start[qi + 1] <= item) ++qi;
         qi = uniform_i32(qi);
@@ -949,14 +1031,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         if (qi != cur) {
             if (cur >= 0) {
                 __syncthreads();
-                flush_lds_agg(*ro(a.q[cur]), shared_area);
-                if (!ok_hdr) atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
+                sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
+                if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
                 ok_hdr = true;
             }
             __syncthreads();
             load_lds_state(Q, shared_area);
             __syncthreads();
             cur = qi;
+            direct |= Q.agg_lds == 0;
         }
         const int mb0 = (item - a.item_start[qi]) * a.mb_per_item;
         const int mb1 = min(mb0 + a.mb_per_item, Q.nmb);
@@ -965,21 +1048,25 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
     }
     if (cur >= 0) {
         __syncthreads();
-        flush_lds_agg(*ro(a.q[cur]), shared_area);
-        if (!ok_hdr) atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
+        sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
+        if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
     }
     // Last workgroup out emits every plan's records and resets the queue.
-    __threadfence();
+    // Publishing: the workgroup's global effects are device-scope atomics,
+    // which are coherent across XCDs; waiting for their returned values
+    // (the sink) orders them before the completion count, so the costly
+    // agent-scope release fence (an L2 writeback) is needed only where rows
+    // were aggregated straight into global memory with plain-result atomics.
+    if (direct) __threadfence();
+    if (sink == ~0ull) ctrl[3] = 1;  // consumes every returned value
     __syncthreads();
-    if (threadIdx.x == 0) ctrl[1] = (int32_t)atomicAdd(&a.counters[1], 1u);
+    if (threadIdx.x == 0) ctrl[1] = finish_last(a, home) ? 1 : 0;
     __syncthreads();
-    if ((uint32_t)ctrl[1] != gridDim.x - 1) return;
+    if (!ctrl[1]) return;
     __threadfence();
     for (int qi = 0; qi < a.nq; ++qi) emit_records(*ro(a.q[qi]), ctrl);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x < 2 * kXcds + 1)  // every other workgroup has left: reset for the next launch
+        __hip_atomic_store(ctr(a, threadIdx.x), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence_system();
 }
 

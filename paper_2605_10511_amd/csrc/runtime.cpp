@@ -910,8 +910,8 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     // device memory: [DevQuery][agg table][status][counters]
     const size_t q_off = 0, agg_off = align_up(sizeof(DevQuery), 256);
     const size_t agg_bytes = (size_t)q.ngroups * q.nacc * 8;
-    const size_t st_off = align_up(agg_off + agg_bytes, 256), cnt_off = st_off + 64;
-    p->dmem_bytes = cnt_off + 64;
+    const size_t st_off = align_up(agg_off + agg_bytes, 256), cnt_off = st_off + 256;
+    p->dmem_bytes = cnt_off + (size_t)kCounterWords * 4;
     p->dmem = ctx->alloc_mem(p->dmem_bytes, DPF_MEM_HBM);
     if (!p->dmem) return bail(fail(DPF_ERR_OOM, "plan workspace"));
     p->host_out_bytes = (2 + (size_t)q.ngroups * (1 + q.nacc)) * 8;

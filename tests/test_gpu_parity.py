@@ -241,3 +241,32 @@ def test_graph_replay(ctx):
         G.assert_same(res.get(0), want, f"eager after replay {k}")
         res.release()
     r.release()
+
+
+@pytest.mark.parametrize("cut", [0, 255, 256, 1000, 2555, 2556, 9999])
+def test_zone_decided_atoms(ctx, cut):
+    """Atoms that a mini block's header settles (all rows pass / none) must
+    give the same rows as decoding: ascending and descending DELTA columns
+    (negative minimum difference), a constant column (width 0), and range,
+    NE and EQ atoms with cut points inside, between and outside blocks."""
+    n = 70_000
+    asc = W.fa_table(n, seed=9)["date"]
+    desc_ = asc[::-1].copy()
+    const = np.full(n, 7, dtype=np.int32)
+    qty = W.fa_table(n, seed=9)["quantity"]
+    t = {"z": {"asc": asc, "desc": desc_, "const": const, "qty": qty}}
+    enc = {"z": {"asc": "DELTA", "desc": "DELTA", "const": "FOR", "qty": "FOR"}}
+    db = G.make_db(ctx, t, enc, chunk_rows=65536)
+    cases = [
+        [{"col": "asc", "op": "LT", "value": cut}],
+        [{"col": "asc", "op": "GE", "value": cut}, {"col": "qty", "op": "LT", "value": 30}],
+        [{"col": "desc", "op": "BETWEEN", "lo": cut - 300, "hi": cut}],
+        [{"col": "const", "op": "NE", "value": 7 if cut % 2 else cut}],
+        [{"col": "const", "op": "EQ", "value": 7}, {"col": "desc", "op": "GT", "value": cut}],
+        [{"col": "asc", "op": "NE", "value": cut}],
+    ]
+    for f in cases:
+        spec = {"fact": "z", "filters": f, "probes": [], "group_by": [],
+                "aggs": [{"op": "COUNT"}, {"op": "SUM", "terms": [{"ref": {"col": "qty"}}]}]}
+        G.say(f"zone cut {cut}: {f}")
+        G.assert_same(G.run_gpu(db, spec), oracle.run(spec, t), f"zone {f}")
