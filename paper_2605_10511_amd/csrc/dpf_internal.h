@@ -67,10 +67,16 @@ struct DevPred {
 };
 
 // Open-addressing table: int32 keys (kEmptyKey = free), payload arrays
-// follow the key array in the same allocation.
+// follow the key array in the same allocation.  When the qualifying keys
+// span at most kMaxBitmapBits values, a membership bitmap over [bmin, bmin +
+// bspan) follows as well: a probe that needs no payload tests one bit.
+constexpr uint64_t kMaxBitmapBits = uint64_t(1) << 25;  // 4 MB
 struct DevHash {
     const int32_t* keys;
     const void* pay[2];
+    const uint32_t* bits;  // nullptr: no bitmap
+    int64_t bmin;
+    uint64_t bspan;
     uint32_t cap_mask;
     int32_t log2cap;
     int32_t npay;
@@ -154,6 +160,8 @@ struct HashBuildArgs {
     int32_t pay64[2];
     uint32_t cap_mask;
     int32_t log2cap;
+    uint32_t* bits;     // membership bitmap (nullptr: none)
+    int64_t bmin;
 };
 
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.

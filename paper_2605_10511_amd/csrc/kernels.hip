@@ -621,11 +621,25 @@ __device__ __forceinline__ int hash_find(CH& h, const uint8_t* smem_shared, int6
     return -1;
 }
 
-// Membership of the lane's four keys (mask bit k: row 64 k + lane is live),
-// probed in lockstep so that the four chains' loads are in flight together.
+// Key-range bitmap test (the table has one: h.bits != nullptr).
+__device__ __forceinline__ bool bitmap_has(CH& h, int64_t key) {
+    const uint64_t d = (uint64_t)key - (uint64_t)h.bmin;
+    if (d >= h.bspan) return false;
+    return (ro(h.bits)[d >> 5] >> (d & 31)) & 1u;
+}
+
+// Membership of the lane's four keys (mask bit k: row 64 k + lane is live):
+// four independent bit tests when the table has a bitmap, else the hash
+// chains probed in lockstep so that their loads are in flight together.
 template <bool kLds>
 __device__ __forceinline__ uint32_t hash_member4(CH& h, const uint8_t* smem_shared, const int64_t key[4],
                                                  uint32_t live) {
+    if (h.bits) {
+        uint32_t found = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) found |= (uint32_t)(((live >> k) & 1u) && bitmap_has(h, key[k])) << k;
+        return found;
+    }
     const int32_t* lkeys = reinterpret_cast<const int32_t*>(smem_shared + h.lds_off);
     cptr<int32_t> gkeys = ro(h.keys);
     uint32_t slot[4];
@@ -720,6 +734,10 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv
             CC& fc = Q.cols[P.fk_col];
             int64_t fk = decode_at(fc, m, i, ok_hdr);
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, ok_hdr);
+            if (P.h.bits && P.pay_slot[0] < 0 && P.pay_slot[1] < 0) {
+                ok = bitmap_has(P.h, fk);  // membership only
+                continue;
+            }
             const bool lds = P.h.lds_off >= 0;
             int slot = lds ? hash_find<true>(P.h, smem_shared, fk) : hash_find<false>(P.h, smem_shared, fk);
             ok = slot >= 0;
@@ -779,7 +797,7 @@ __device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, const
 // 64 k + lane -> bit k).  kEager: the plan's one string atom comes last and
 // its loads are issued before the integer atoms run, so both wait for memory
 // once, together.
-template <bool kEager>
+template <bool kEager, bool kStr>
 __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m, int lane, int nvalid,
                                                 bool& ok_hdr) {
     uint32_t mask = 0;
@@ -795,8 +813,14 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
     for (int a = 0; a < (kEager ? npreds - 1 : npreds); ++a) {
         CP& P = Q.preds[a];
         if (!kEager && P.kind == PK_STR) {
-            if (P.n1 >= 4 && P.n2 >= 4) mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
-            else mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            if (!kStr) {
+                ok_hdr = false;  // unreachable: the launch picks the string instantiation
+                return 0;
+            } else if (P.n1 >= 4 && P.n2 >= 4) {
+                mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            } else {
+                mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+            }
         } else {
             const int z = zone_test(Q.cols[P.col], P, m);
             if (z == 1) continue;
@@ -816,6 +840,7 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
     return mask;
 }
 
+template <bool kStr>
 __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
                              int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
@@ -851,8 +876,8 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
                                  : hash_member4<false>(P0.h, smem_shared, fk, mask);
     } else {
         mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
-                   ? filter_tile<true>(Q, W, m, lane, nvalid, ok_hdr)
-                   : filter_tile<false>(Q, W, m, lane, nvalid, ok_hdr);
+                   ? (kStr ? filter_tile<true, kStr>(Q, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
+                   : filter_tile<false, kStr>(Q, W, m, lane, nvalid, ok_hdr);
     }
     if (__ballot(mask != 0) == 0) return;
 
@@ -998,7 +1023,7 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 // ---------------------------------------------------------------------------
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
-template <int NW>
+template <int NW, bool kStr>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
@@ -1043,7 +1068,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         }
         const int mb0 = (item - a.item_start[qi]) * a.mb_per_item;
         const int mb1 = min(mb0 + a.mb_per_item, Q.nmb);
-        for (int m = mb0 + wave; m < mb1; m += NW) process_tile(Q, shared_area, W, m, lane, npend, ok_hdr);
+        for (int m = mb0 + wave; m < mb1; m += NW) process_tile<kStr>(Q, shared_area, W, m, lane, npend, ok_hdr);
         if (npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
@@ -1151,6 +1176,10 @@ __global__ __launch_bounds__(kBlock) void hash_insert_kernel(const HashBuildArgs
                 if (n > A.cap_mask) { flags |= ST_CAPACITY; break; }
                 int32_t prev = atomicCAS(&A.keys[s], kEmptyKey, kk);
                 if (prev == kEmptyKey) {
+                    if (A.bits) {
+                        const uint64_t d = (uint64_t)(key[k] - A.bmin);
+                        atomicOr(&A.bits[d >> 5], 1u << (d & 31));
+                    }
                     for (int j = 0; j < A.npay; ++j) {
                         if (A.pay64[j]) reinterpret_cast<int64_t*>(A.pay[j])[s] = pay[j][k];
                         else reinterpret_cast<int32_t*>(A.pay[j])[s] = (int32_t)pay[j][k];
@@ -1397,15 +1426,18 @@ __global__ void frag_reset_counts(unsigned long long* c, int n) {
     if (threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-template <int NW>
+// Two instantiations per workgroup size: plans with a string atom need the
+// string stage's registers; without it the kernel fits in about half the
+// VGPRs and keeps more waves resident.
+template <int NW, bool kStr>
 hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW, kStr>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    hipLaunchKernelGGL(fused_kernel<NW>, dim3(grid), dim3(NW * kWave), lds_bytes, s, a);
+    hipLaunchKernelGGL((fused_kernel<NW, kStr>), dim3(grid), dim3(NW * kWave), lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -1415,9 +1447,12 @@ size_t fused_wave_area_bytes(bool str, bool pend) { return wave_area_bytes(str, 
 
 hipError_t launch_fused(const BatchArgs& a, int waves, int grid, size_t lds_bytes, hipStream_t s) {
     switch (waves) {
-        case 4: return launch_fused_nw<4>(a, grid, lds_bytes, s);
-        case 8: return launch_fused_nw<8>(a, grid, lds_bytes, s);
-        case 16: return launch_fused_nw<16>(a, grid, lds_bytes, s);
+        case 4: return a.str_stage ? launch_fused_nw<4, true>(a, grid, lds_bytes, s)
+                                   : launch_fused_nw<4, false>(a, grid, lds_bytes, s);
+        case 8: return a.str_stage ? launch_fused_nw<8, true>(a, grid, lds_bytes, s)
+                                   : launch_fused_nw<8, false>(a, grid, lds_bytes, s);
+        case 16: return a.str_stage ? launch_fused_nw<16, true>(a, grid, lds_bytes, s)
+                                    : launch_fused_nw<16, false>(a, grid, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }

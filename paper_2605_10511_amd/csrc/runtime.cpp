@@ -582,15 +582,21 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
         pay_off[j] = bytes;
         bytes += cap * (pay64[j] ? 8 : 4);
     }
+    // membership bitmap over the qualifying keys' range (not copied to LDS)
+    const uint64_t kspan = count ? (uint64_t)(mm[1] - mm[0]) + 1 : 0;
+    const bool use_bits = count && (uint64_t)(mm[1] - mm[0]) < kMaxBitmapBits;
+    const size_t bits_off = align_up(bytes, 256);
+    const size_t bits_words = use_bits ? (size_t)((kspan + 31) / 32) : 0;
+    const size_t alloc_bytes = use_bits ? bits_off + bits_words * 4 : bytes;
     dpf_hash h = new (std::nothrow) dpf_hash_s();
     if (!h) return fail(DPF_ERR_OOM, "hash");
     h->ctx = ctx;
-    h->mem = ctx->alloc_mem(bytes, DPF_MEM_HBM);
+    h->mem = ctx->alloc_mem(alloc_bytes, DPF_MEM_HBM);
     if (!h->mem) {
         delete h;
         return fail(DPF_ERR_OOM, "hash table allocation failed");
     }
-    h->bytes = bytes;
+    h->bytes = alloc_bytes;  // device footprint (the LDS copy is dev.bytes: keys and payloads)
     auto bail = [&](dpf_status st, const std::string& m) {
         ctx->free_mem(h->mem, DPF_MEM_HBM);
         delete h;
@@ -603,7 +609,10 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     }
     A.cap_mask = (uint32_t)(cap - 1);
     A.log2cap = log2cap;
+    A.bits = use_bits ? (uint32_t*)((uint8_t*)h->mem + bits_off) : nullptr;
+    A.bmin = use_bits ? mm[0] : 0;
     hipError_t e = launch_fill_i32((int32_t*)h->mem, kEmptyKey, (int64_t)cap, s);
+    if (e == hipSuccess && use_bits) e = launch_fill_i32((int32_t*)A.bits, 0, (int64_t)bits_words, s);
     if (e == hipSuccess) e = hipMemcpyAsync(scratch + args_off, &A, sizeof A, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_hash_insert((const HashBuildArgs*)(scratch + args_off), grid, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&status, A.status, 4, hipMemcpyDeviceToHost, s);
@@ -624,6 +633,9 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     d.pay64[1] = pay64[1];
     d.lds_off = -1;
     d.bytes = (uint32_t)bytes;
+    d.bits = A.bits;
+    d.bmin = A.bmin;
+    d.bspan = use_bits ? kspan : 0;
     dpf_hash_stats& st = h->stats;
     st.entries = (int64_t)count;
     st.capacity = (int64_t)cap;
@@ -662,7 +674,8 @@ constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
 constexpr int64_t kDefaultMbPerItem = 64;  // 16,384 rows
-constexpr int kTargetWavesPerCU = 16;  // the fused kernel's register budget allows 4 waves per SIMD
+constexpr int kTargetWavesPerCU = 16;       // string stage's register budget: 4 waves per SIMD
+constexpr int kTargetWavesPerCUNoStr = 28;  // without it: 7 waves per SIMD
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
 // shared area within budget; fills lds offsets and lds_shared.
@@ -1079,7 +1092,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
             return fail(DPF_ERR_UNSUPPORTED, "plan LDS needs exceed the workgroup limit; lower lds_hash_bytes");
         const int lds_cu = 160 * 1024;
         int wg = o.wg_per_cu;
-        if (wg <= 0) wg = std::max(1, kTargetWavesPerCU / waves);
+        if (wg <= 0) wg = std::max(1, (str ? kTargetWavesPerCU : kTargetWavesPerCUNoStr) / waves);
         wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
         const int grid = std::max(1, ctx->ncu * wg);
         // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
