@@ -51,7 +51,7 @@ __device__ __forceinline__ uint4 ld4(cptr<uint4> g, uint32_t i) {
 }
 
 constexpr int kPendCap = 320;   // per-wave survivor queue (64 pending + one mini block)
-constexpr int kSegIters = 8;    // 16-byte string loads per lane per segment (8 KB per wave)
+constexpr int kSegIters = 2;    // 16-byte string loads per lane per segment (2 KB per wave, double-buffered)
 
 // ---------------------------------------------------------------------------
 // Wave helpers
@@ -373,9 +373,15 @@ __device__ __forceinline__ void check_word(const StrLds& L, uint32_t q, uint32_t
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // One mini block's string test between issuing its loads and using them.
+// One heap segment in registers: lane l holds bytes [16 (base + it * 64 + l),
+// +16) in W[it]; tx, ty are the two words after the segment (for lane 63).
+struct Seg {
+    uint4 W[kSegIters];
+    uint32_t tx, ty;
+};
+
 struct StrTile {
-    uint4 W[kSegIters];    // heap segment: lane l holds bytes [16 (base + it * 64 + l), +16)
-    uint32_t tx, ty;       // lane 63: the two words after the segment
+    Seg cur;               // the segment being compared (the first, after str_begin)
     uint64_t lraw[4];      // packed lengths of rows 4 lane .. 4 lane + 3, unshifted
     cptr<uint4> g;         // 16-byte-aligned start of the heap bytes
     const uint8_t* gp;     // the same address, generic
@@ -394,7 +400,7 @@ constexpr int kRawBufferWord3 = 0x00020000;
 // [16 v, 16 v + 16) from the 16-byte-aligned start) into W; vectors past
 // nvec read as zero through the buffer range check.  The per-lane offset is
 // the only VGPR address; the slots differ by immediate offsets.
-__device__ __forceinline__ void load_segment(StrTile& S, uint32_t base, uint32_t nvec, int lane) {
+__device__ __forceinline__ void load_segment(Seg& G, const StrTile& S, uint32_t base, uint32_t nvec, int lane) {
     const uint32_t nbytes = (nvec + 1u - base) * 16u;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(S.gp + (uint64_t)base * 16u), 0, (int)nbytes, kRawBufferWord3);
@@ -408,14 +414,14 @@ __device__ __forceinline__ void load_segment(StrTile& S, uint32_t base, uint32_t
         const int off = it * kWave * 16;  // below 4096: immediate on vo; else on vo2
         const u32x4 t = off < 4096 ? __builtin_amdgcn_raw_buffer_load_b128(r, vo + off, 0, 0)
                                    : __builtin_amdgcn_raw_buffer_load_b128(r, vo2 + (off - 4096), 0, 0);
-        S.W[it] = make_uint4(t.x, t.y, t.z, t.w);
+        G.W[it] = make_uint4(t.x, t.y, t.z, t.w);
     }
     const uint32_t vt = base + kSegIters * kWave;  // wave-uniform: scalar load
-    S.tx = S.ty = 0;
+    G.tx = G.ty = 0;
     if (vt <= nvec) {
         const u32x2 t = ((cptr<u32x2>)S.g)[2 * vt];
-        S.tx = t.x;
-        S.ty = t.y;
+        G.tx = t.x;
+        G.ty = t.y;
     }
 }
 
@@ -440,18 +446,18 @@ __device__ __forceinline__ void str_begin(CC& c, int m, int lane, StrTile& S) {
         S.lraw[j] = S.b ? *(cptr<u64_a4>)(h.w + (pj >> 5)) : 0;
     }
     if (S.ok) {
-        load_segment(S, 0, nvec, lane);
+        load_segment(S.cur, S, 0, nvec, lane);
     } else {
 #pragma unroll
-        for (int it = 0; it < kSegIters; ++it) S.W[it] = make_uint4(0u, 0u, 0u, 0u);
-        S.tx = S.ty = 0;
+        for (int it = 0; it < kSegIters; ++it) S.cur.W[it] = make_uint4(0u, 0u, 0u, 0u);
+        S.cur.tx = S.cur.ty = 0;
     }
 }
 
 // Neighbour words of lane's segment slot it: the next lane's first two words
 // (for lane 63, those of the next slot's lane 0, or the words after the
 // segment).
-__device__ __forceinline__ void next_words(const StrTile& S, int it, int lane, uint32_t& nx, uint32_t& nx2) {
+__device__ __forceinline__ void next_words(const Seg& S, int it, int lane, uint32_t& nx, uint32_t& nx2) {
     nx = dpp_u32<kDppWaveShl1>(S.W[it].x);
     nx2 = dpp_u32<kDppWaveShl1>(S.W[it].y);
     uint32_t lx = S.tx, ly = S.ty;
@@ -502,16 +508,21 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;  // first 4 bytes
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
     cptr<uint8_t> hs = ro(c.heap + S.h0);
+    Seg nxt;
     for (uint32_t base = 0;; base += kSegIters * kWave) {
+        // Double buffering: the next segment's loads are in flight while
+        // this one is compared.
+        const bool more = base + kSegIters * kWave < nvec;
+        if (more) load_segment(nxt, S, base + kSegIters * kWave, nvec, lane);
         // Hot loop: bit (4 it + wd) of hits marks a word whose 4-byte windows
         // match a prefix.
         uint32_t hits = 0;
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
             if (base + (uint32_t)it * kWave > nvec) break;  // slots past the mini block hold zeros
-            const uint4 w = S.W[it];
+            const uint4 w = S.cur.W[it];
             uint32_t nx, nx2;
-            next_words(S, it, lane, nx, nx2);
+            next_words(S.cur, it, lane, nx, nx2);
             const uint32_t e[5] = {w.x, w.y, w.z, w.w, nx};
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
@@ -535,9 +546,9 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
             for (int it = 0; it < kSegIters; ++it) {
                 uint32_t hm = (hits >> (4 * it)) & 0xFu;
                 if (__ballot(hm != 0) == 0) continue;
-                const uint4 w = S.W[it];
+                const uint4 w = S.cur.W[it];
                 uint32_t nx, nx2;
-                next_words(S, it, lane, nx, nx2);
+                next_words(S.cur, it, lane, nx, nx2);
                 const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
                 while (hm) {
                     const int wd = __builtin_ctz(hm);
@@ -549,8 +560,8 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
                 }
             }
         }
-        if (base + kSegIters * kWave >= nvec) break;
-        load_segment(S, base + kSegIters * kWave, nvec, lane);
+        if (!more) break;
+        S.cur = nxt;
     }
     wave_lds_sync();
     uint32_t res = 0;
@@ -1024,7 +1035,7 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
 template <int NW, bool kStr>
-__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void fused_kernel(BatchArgs a) {
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr ? 5 : 4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
     uint8_t* shared_area = smem + 64;
