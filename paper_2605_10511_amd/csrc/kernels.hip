@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
     uint8_t* shared_area = smem + 64;
     const bool str_stage = a.str_stage != 0;
     const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform_i32(threadIdx.x >> 6);  // uniform: mini-block headers become scalar loads
     const bool pend_stage = a.pend_stage != 0;
     const WaveArea W =
         wave_area(smem + 64 + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage, pend_stage), pend_stage);
