@@ -52,6 +52,7 @@ __device__ __forceinline__ uint4 ld4(cptr<uint4> g, uint32_t i) {
 
 constexpr int kPendCap = 320;   // per-wave survivor queue (64 pending + one mini block)
 constexpr int kSegIters = 2;    // 16-byte string loads per lane per segment (2 KB per wave, double-buffered)
+constexpr int kRecCap = 64;     // per-wave queue of string words with a prefix hit (16 B each)
 
 // ---------------------------------------------------------------------------
 // Wave helpers
@@ -333,6 +334,7 @@ struct StrLds {
     uint32_t* offs;    // [257] row start offsets within the mini block's heap
     uint32_t* first1;  // [256] leftmost s1 start (0xffffffff: none)
     uint32_t* last2;   // [256] rightmost s2 start + 1 (0: none)
+    uint4* recs;       // [kRecCap] words with a prefix hit: {byte offset, word, next, the one after}
 };
 
 // Records an s1 and/or s2 start at heap position pos of the mini block: the
@@ -468,6 +470,19 @@ __device__ __forceinline__ void next_words(const Seg& S, int it, int lane, uint3
     if (lane == kWave - 1) { nx = lx; nx2 = ly; }
 }
 
+// Checks queued hit words, one per lane (all lanes at once: a wave pays
+// for the check once per batch of hits, not once per hit).
+__device__ __forceinline__ void drain_records(const StrLds& L, int nrec, uint32_t s0, uint32_t total,
+                                              const StrPattern& P1, const StrPattern& P2, CP& p,
+                                              cptr<uint8_t> hs, int lane) {
+    wave_lds_sync();
+    for (int j = lane; j < nrec; j += kWave) {
+        const uint4 r = L.recs[j];
+        check_word(L, r.x, r.y, r.z, r.w, s0, total, P1, P2, p, hs);
+    }
+    wave_lds_sync();
+}
+
 // Returns the 4-bit match mask of the lane's rows (row 64 k + lane -> bit k)
 // for the mini block whose loads str_begin issued; clears ok on corruption.
 // kMasked: some word is shorter than 4 bytes, so 4-byte windows are masked.
@@ -508,22 +523,24 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;  // first 4 bytes
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
     cptr<uint8_t> hs = ro(c.heap + S.h0);
+    const uint32_t total_b = (uint32_t)(S.h1 - S.h0);
+    int nrec = 0;
     Seg nxt;
     for (uint32_t base = 0;; base += kSegIters * kWave) {
         // Double buffering: the next segment's loads are in flight while
         // this one is compared.
         const bool more = base + kSegIters * kWave < nvec;
         if (more) load_segment(nxt, S, base + kSegIters * kWave, nvec, lane);
-        // Hot loop: bit (4 it + wd) of hits marks a word whose 4-byte windows
-        // match a prefix.
-        uint32_t hits = 0;
+        // Hot loop.  A word whose 4-byte windows match a prefix is queued
+        // with its two successors in LDS (a rare, wave-uniform branch).
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
             if (base + (uint32_t)it * kWave > nvec) break;  // slots past the mini block hold zeros
             const uint4 w = S.cur.W[it];
             uint32_t nx, nx2;
             next_words(S.cur, it, lane, nx, nx2);
-            const uint32_t e[5] = {w.x, w.y, w.z, w.w, nx};
+            const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
+            const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
                 const uint32_t w0 = e[wd];
@@ -537,32 +554,22 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
                 else
                     hit = (w0 == q1) | (w1 == q1) | (w2 == q1) | (w3 == q1) | (w0 == q2) | (w1 == q2) |
                           (w2 == q2) | (w3 == q2);
-                hits |= hit ? (1u << (4 * it + wd)) : 0u;
-            }
-        }
-        // Rare path: the hit words are checked from the same registers.
-        if (__ballot(hits != 0)) {
-#pragma unroll
-            for (int it = 0; it < kSegIters; ++it) {
-                uint32_t hm = (hits >> (4 * it)) & 0xFu;
-                if (__ballot(hm != 0) == 0) continue;
-                const uint4 w = S.cur.W[it];
-                uint32_t nx, nx2;
-                next_words(S.cur, it, lane, nx, nx2);
-                const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
-                while (hm) {
-                    const int wd = __builtin_ctz(hm);
-                    hm &= hm - 1;
-                    const uint32_t e0 = wd == 0 ? w.x : wd == 1 ? w.y : wd == 2 ? w.z : w.w;
-                    const uint32_t e1 = wd == 0 ? w.y : wd == 1 ? w.z : wd == 2 ? w.w : nx;
-                    const uint32_t e2 = wd == 0 ? w.z : wd == 1 ? w.w : wd == 2 ? nx : nx2;
-                    check_word(L, q0 + 4u * (uint32_t)wd, e0, e1, e2, s0, S.h1 - S.h0, P1, P2, p, hs);
+                const uint64_t hb = __ballot(hit);
+                if (hb) {
+                    const int nh = (int)__popcll(hb);
+                    if (nrec + nh > kRecCap) {
+                        drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
+                        nrec = 0;
+                    }
+                    if (hit) L.recs[nrec + bits_below(hb)] = make_uint4(q0 + 4 * wd, e[wd], e[wd + 1], e[wd + 2]);
+                    nrec += nh;
                 }
             }
         }
         if (!more) break;
         S.cur = nxt;
     }
+    if (nrec) drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
     wave_lds_sync();
     uint32_t res = 0;
 #pragma unroll
@@ -789,6 +796,7 @@ struct WaveArea {
     uint32_t* offs;    // [260] string row offsets
     uint32_t* first1;  // [256] leftmost s1 start per row
     uint32_t* last2;   // [256] rightmost s2 start + 1 per row
+    uint4* recs;       // [kRecCap] string words with a prefix hit
 };
 
 __device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int& npend, int lane,
@@ -814,7 +822,7 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
-    const StrLds L{W.offs, W.first1, W.last2};
+    const StrLds L{W.offs, W.first1, W.last2, W.recs};
     const int npreds = Q.npreds;
     CP& PL = Q.preds[npreds - 1];
     StrTile S;
@@ -908,7 +916,7 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
 // offsets, s1 / s2 starts and hit queue -- a wave never uses both at once
 // (a mini block's string test finishes before its survivors are queued).
 constexpr size_t kSlotBytes = kMaxSlots * kWave * 8;
-constexpr size_t kStrBytes = 260 * 4 + 2 * 256 * 4;
+constexpr size_t kStrBytes = 260 * 4 + 2 * 256 * 4 + kRecCap * 16;
 
 __host__ __device__ constexpr size_t wave_area_bytes(bool str_stage, bool pend_stage) {
     return (pend_stage ? kPendCap * 4 : 0) + (str_stage && kStrBytes > kSlotBytes ? kStrBytes : kSlotBytes);
@@ -922,6 +930,7 @@ __device__ __forceinline__ WaveArea wave_area(uint8_t* p, bool pend_stage) {
     W.offs = reinterpret_cast<uint32_t*>(shared);
     W.first1 = W.offs + 260;
     W.last2 = W.first1 + 256;
+    W.recs = reinterpret_cast<uint4*>(W.last2 + 256);
     return W;
 }
 
