@@ -38,6 +38,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_10511_amd", "csrc", f) for f in ("kernels.hip", "dpf_internal.h")]
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per fused launch from the committed counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-kernel
+    calibration), or None when the kernel sources changed since the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", f"fused_kernel_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("    "):
+                k, v = line.strip().split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_source_sha256():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def workload(name: str, scale: float):
     from datagen import workloads as W
     if name == "wide":
@@ -201,8 +236,9 @@ def main():
         "hbm_peak_frac": gbps / HBM_PEAK_GBPS,
         "launches_per_query": launches,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "fused_kernel", "kernel_ms": kern_ms},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
+                     "kernel": "fused_kernel", "kernel_ms": kern_ms,
+                     "algorithmic_bytes": alg_bytes},
         "fragmented": frag,
         "fused_speedup_vs_fragmented": (frag["ms_per_step"] / ms_per_step) if frag else None,
         "cpu_baseline": cpu,
