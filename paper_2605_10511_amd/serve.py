@@ -18,7 +18,9 @@ Requests arrive over time (Poisson in the benchmark).  The server
 
 Tables larger than the residency budget are placed in pinned host memory
 mapped into the device and scanned over the host link (Section 3.1's zero
-copy path), on a stream of their own.
+copy path).  Requests on such tables run on a stream of their own and never
+share a batch with resident-table requests: a launch finishes when its
+slowest plan does, and a host-link scan takes tens of milliseconds.
 """
 from __future__ import annotations
 
@@ -52,7 +54,7 @@ class _Batch:
 
 class Server:
     def __init__(self, ctx: dpf.Context, db: dpf.Database, nstreams: int = 4, slots: int = 8,
-                 state_budget: int = 4 << 30, placements: dict | None = None):
+                 state_budget: int = 4 << 30, placements: dict | None = None, host_tables=()):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -63,12 +65,17 @@ class Server:
         self.hashes: dict[str, dpf.Hash] = {}
         self.placements = placements or {}
         self.hash_builds = 0
+        self.hash_build_s = 0.0
+        self.host_tables = set(host_tables)
+        if self.host_tables:
+            self.host_stream = torch.cuda.Stream()  # default priority
 
     # -- preparation -------------------------------------------------------
     def _hash(self, pr: dict) -> dpf.Hash:
         key = json.dumps([pr["dim"], pr["key"], pr.get("filters", []), pr.get("payloads", [])], sort_keys=True)
         h = self.hashes.get(key)
         if h is None:
+            t0 = time.perf_counter()
             cols = self.db.tables[pr["dim"]]
             used = [pr["key"]] + [p["col"] for p in pr.get("filters", [])] + list(pr.get("payloads", []))
             sub = {c: cols[c] for c in dict.fromkeys(used)}
@@ -78,7 +85,14 @@ class Server:
             s.synchronize()  # later batches on other streams read it
             self.hashes[key] = h
             self.hash_builds += 1
+            self.hash_build_s += time.perf_counter() - t0
         return h
+
+    def warm(self, reqs: list):
+        """Build (cache) every dimension hash table ``reqs`` will probe."""
+        for r in reqs:
+            for pr in r.spec.get("probes", []):
+                self._hash(pr)
 
     def prepare(self, r: Request):
         hashes = [self._hash(pr) for pr in r.spec.get("probes", [])]
@@ -92,6 +106,8 @@ class Server:
         torch = self.torch
         reqs = sorted(reqs, key=lambda r: r.t)
         ready = collections.deque()
+        ready_host = collections.deque()
+        host_busy = False
         inflight: list[_Batch] = []
         free = list(range(len(self.streams)))
         used = 0
@@ -99,7 +115,7 @@ class Server:
         done = []
         i = 0
         t0 = time.perf_counter()
-        while i < len(reqs) or ready or inflight:
+        while i < len(reqs) or ready or ready_host or inflight:
             now = time.perf_counter() - t0
             if t_limit is not None and now > t_limit and not inflight:
                 break
@@ -107,7 +123,7 @@ class Server:
             # arrivals: prepare in arrival order
             while i < len(reqs) and reqs[i].t <= now:
                 self.prepare(reqs[i])
-                ready.append(reqs[i])
+                (ready_host if reqs[i].table in self.host_tables else ready).append(reqs[i])
                 i += 1
                 progressed = True
             # completions
@@ -121,8 +137,11 @@ class Server:
                         r.plan = None
                     b.result.release()
                     used -= b.footprint
-                    nin -= len(b.reqs)
-                    free.append(b.stream)
+                    if b.stream >= 0:
+                        nin -= len(b.reqs)
+                        free.append(b.stream)
+                    else:
+                        host_busy = False
                     inflight.remove(b)
                     done.extend(b.reqs)
                     progressed = True
@@ -154,13 +173,28 @@ class Server:
                 used += fp
                 nin += len(batch)
                 progressed = True
+            # host-table requests: one at a time on their own stream
+            if ready_host and not host_busy:
+                r = ready_host.popleft()
+                b = _Batch()
+                b.stream = -1
+                b.reqs = [r]
+                b.footprint = r.footprint
+                r.issued = time.perf_counter() - t0
+                b.result = dpf.execute(self.ctx, [r.plan], stream=self.host_stream)
+                b.event = torch.cuda.Event()
+                b.event.record(self.host_stream)
+                inflight.append(b)
+                used += r.footprint
+                host_busy = True
+                progressed = True
             if not progressed:
                 nxt = reqs[i].t - (time.perf_counter() - t0) if i < len(reqs) else 0.0
                 if not inflight and nxt > 0:
                     time.sleep(min(nxt, 0.002))
                 else:
                     time.sleep(20e-6)
-        for r in ready:
+        for r in list(ready) + list(ready_host):
             if r.plan is not None:
                 r.plan.release()
                 r.plan = None

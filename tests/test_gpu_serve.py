@@ -83,3 +83,23 @@ def test_state_budget_serialises_batches(env):
     for r in done:
         G.assert_same(r.rows, oracle.run(r.spec, tables), "budget-limited")
     srv.close()
+
+
+def test_host_table_requests_run_apart(env):
+    """Requests on a host-mapped table run on their own stream, never in a
+    resident batch; every result still equals the oracle's."""
+    from paper_2605_10511_amd import serve
+    ctx, db, tables = env
+    host = W.union_table(120_000, seed=55, dims={k: tables[k] for k in ("date", "customer", "supplier", "part")})
+    db.add_table("host", host, W.FA_ENCODINGS, placement="HOST_MAPPED")
+    tabs = {**tables, "host": host}
+    reqs = [serve.Request(t, k, s, "res") for t, k, s in W.serve_requests(13, 300.0, 0.05, "res")]
+    reqs += [serve.Request(t, k, s, "host") for t, k, s in W.serve_requests(14, 100.0, 0.05, "host", stream="h")]
+    G.say(f"serving {len(reqs)} requests, some on a host-mapped table")
+    srv = serve.Server(ctx, db, nstreams=3, slots=8, state_budget=1 << 30, host_tables=("host",))
+    srv.warm(reqs)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    for r in done:
+        G.assert_same(r.rows, oracle.run(r.spec, tabs), f"served {r.table}/{r.template}")
+    srv.close()
