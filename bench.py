@@ -435,9 +435,12 @@ def bench_serve(args):
 
     srv = Server(ctx, db, nstreams=4, slots=8, state_budget=4 << 30,
                  host_tables=("host",) if args.host_rows > 0 else ())
-    # warm: one request of each template
-    warm = [Request(0.0, "FA", W.fa_query("res"), "res"),
-            Request(0.0, "SJ", W.sj_query("res"), "res")]
+    # warm, untimed: a burst of 48 resident requests (and 2 host-table ones)
+    # fills the memory pool's size classes and loads every code path
+    warm = [Request(0.0, k, sp, "res") for _, k, sp in W.serve_requests(99, 1000.0, 0.048, "res", stream="warm")]
+    if args.host_rows > 0:
+        warm += [Request(0.0, k, sp, "host") for _, k, sp in W.serve_requests(98, 100.0, 0.02, "host", stream="warm")][:2]
+    srv.warm(warm)
     srv.run(warm)
     per_rate = []
     sample = []
@@ -521,6 +524,7 @@ def bench_serve(args):
                                + (f" plus 1 QPS on a {args.host_rows:,}-row host-mapped table"
                                   if args.host_rows > 0 else ""),
                    "streams": 4, "slots": 8, "state_budget_bytes": 4 << 30,
+                   "host_table_knobs": srv.host_knobs,
                    "resident_compressed_bytes": res_bytes},
         "rates": per_rate,
         "hash_builds": srv.hash_builds,

@@ -22,6 +22,9 @@
  *    call, except where a call's description says it synchronises.
  *  - Device memory (HBM) and pinned, device-mapped host memory come from the
  *    context's allocator (hipMalloc / hipHostMalloc when none is given).
+ *    Blocks of up to 64 MB are recycled inside the context through
+ *    power-of-two size classes instead of being freed (hipFree synchronises
+ *    the device); they return to the allocator in dpf_ctx_destroy.
  */
 #ifndef DPF_H
 #define DPF_H
@@ -77,6 +80,7 @@ typedef struct {
  * only encoding, column inspection and host decoding work (placement must be
  * DPF_PLACE_HOST).  allocator may be NULL. */
 dpf_status dpf_ctx_create(int32_t device, const dpf_allocator* allocator, dpf_ctx* out);
+/* Synchronises the device, then frees everything the context still holds. */
 void dpf_ctx_destroy(dpf_ctx ctx);
 
 typedef struct {
@@ -293,16 +297,20 @@ typedef struct {
     int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = 16384) */
     int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto)     */
     int32_t waves_per_wg;    /* FUSED: 4, 8 or 16 waves per workgroup (0 = auto)       */
+    int32_t max_workgroups;  /* FUSED: cap on the grid (0 = none).  A scan bound by the
+                                host link needs few workgroups; a small grid leaves the
+                                other CUs' slots and memory queues to concurrent work */
 } dpf_exec_opts;
 
 /* Enqueues n >= 1 plans on stream.  FUSED runs them all in ONE launch of the
  * persistent kernel, which claims (plan, row range) work items from a device
  * queue; FRAGMENTED runs each plan as a sequence of separate kernels with
  * materialised intermediates (it allocates on first use and is not meant for
- * graph capture).  FUSED with n <= 64 allocates nothing and is
- * graph-capturable.  A plan must not be in two executions at once.  *out
- * receives a result handle that is readable after the stream has
- * synchronised. */
+ * graph capture).  FUSED with n <= 64 allocates no device memory and is
+ * graph-capturable.  Outside stream capture the call records a completion
+ * event on the stream for dpf_result_release.  A plan must not be in two
+ * executions at once.  *out receives a result handle that is readable after
+ * the stream has synchronised. */
 dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
                        dpf_stream stream, dpf_result* out);
 
@@ -315,6 +323,9 @@ dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_
  * stays valid until the next call on the same result or its release. */
 dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* ncols,
                           const int64_t** rows);
+/* Waits for the execution to finish (its completion event; a captured
+ * execution has none, and its replays are the caller's to order), then drops
+ * the result's references to its plans, whose memory may be recycled. */
 void dpf_result_release(dpf_result res);
 
 #ifdef __cplusplus

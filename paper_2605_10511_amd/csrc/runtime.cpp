@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -50,8 +51,18 @@ struct dpf_ctx_s {
     int64_t hbm = 0;
     std::atomic<int64_t> launches{0};
 
-    void* alloc_mem(size_t bytes, int kind) {
-        if (bytes == 0) bytes = 16;
+    // Allocations up to kPoolMax (plan workspaces, result buffers, hash
+    // tables, build scratch) are recycled through power-of-two size classes:
+    // in ROCm hipFree and hipHostFree synchronise the whole device, which
+    // would stall a serving loop behind every kernel in flight on every
+    // plan release.  Memory is returned when the context is destroyed.
+    static constexpr size_t kPoolMin = 4096, kPoolMax = size_t(64) << 20;
+    static constexpr int kClasses = 15;  // 4 KB .. 64 MB
+    std::mutex pool_mu;
+    std::unordered_map<void*, std::pair<int, int>> pooled;  // block -> (kind, class)
+    std::vector<void*> pool_free[2][kClasses];
+
+    void* raw_alloc(size_t bytes, int kind) {
         if (custom) return alloc.alloc(alloc.user, bytes, kind);
         void* p = nullptr;
         if (kind == DPF_MEM_HBM) {
@@ -61,11 +72,47 @@ struct dpf_ctx_s {
         }
         return p;
     }
-    void free_mem(void* p, int kind) {
-        if (!p) return;
+    void raw_free(void* p, int kind) {
         if (custom) { alloc.free(alloc.user, p, kind); return; }
         if (kind == DPF_MEM_HBM) (void)hipFree(p);
         else (void)hipHostFree(p);
+    }
+    void* alloc_mem(size_t bytes, int kind) {
+        if (bytes == 0) bytes = 16;
+        if (bytes > kPoolMax) return raw_alloc(bytes, kind);
+        int c = 0;
+        while ((kPoolMin << c) < bytes) ++c;
+        {
+            std::lock_guard<std::mutex> g(pool_mu);
+            std::vector<void*>& fl = pool_free[kind][c];
+            if (!fl.empty()) {
+                void* p = fl.back();
+                fl.pop_back();
+                return p;
+            }
+        }
+        void* p = raw_alloc(kPoolMin << c, kind);
+        if (p) {
+            std::lock_guard<std::mutex> g(pool_mu);
+            pooled[p] = {kind, c};
+        }
+        return p;
+    }
+    void free_mem(void* p, int kind) {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> g(pool_mu);
+            auto it = pooled.find(p);
+            if (it != pooled.end()) {
+                pool_free[it->second.first][it->second.second].push_back(p);
+                return;
+            }
+        }
+        raw_free(p, kind);
+    }
+    ~dpf_ctx_s() {
+        if (device >= 0) (void)hipDeviceSynchronize();
+        for (auto& kv : pooled) raw_free(kv.first, kv.second.first);
     }
     void* device_ptr(void* host) {  // device address of pinned host memory
         void* d = nullptr;
@@ -124,6 +171,7 @@ struct dpf_plan_s {
 };
 
 struct dpf_result_s {
+    hipEvent_t done = nullptr;  // recorded after the launch (absent under stream capture)
     std::vector<dpf_plan> plans;
     std::vector<std::vector<int64_t>> rows;
     std::vector<int32_t> ncols;
@@ -1095,7 +1143,8 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         int wg = o.wg_per_cu;
         if (wg <= 0) wg = std::max(1, (str ? kTargetWavesPerCU : kTargetWavesPerCUNoStr) / waves);
         wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
-        const int grid = std::max(1, ctx->ncu * wg);
+        int grid = std::max(1, ctx->ncu * wg);
+        if (o.max_workgroups > 0) grid = std::min(grid, o.max_workgroups);
         // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
         // shrunk for small batches so that every workgroup gets about four
         // items, but never below one mini block per wave.
@@ -1119,6 +1168,16 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
     }
     dpf_result r = new (std::nothrow) dpf_result_s();
     if (!r) return fail(DPF_ERR_OOM, "result");
+    // Completion event for the release (not under graph capture, where the
+    // caller owns the ordering of replays).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+        if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) r->done = nullptr;
+        else if (hipEventRecord(r->done, s) != hipSuccess) {
+            (void)hipEventDestroy(r->done);
+            r->done = nullptr;
+        }
+    }
     for (int i = 0; i < n; ++i) {
         plans[i]->refs++;
         plans[i]->issued = true;
@@ -1181,6 +1240,11 @@ extern "C" dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups
 
 extern "C" void dpf_result_release(dpf_result res) {
     if (!res) return;
+    if (res->done) {
+        // the plans' memory may be recycled below: wait for the launch
+        (void)hipEventSynchronize(res->done);
+        (void)hipEventDestroy(res->done);
+    }
     for (dpf_plan p : res->plans) dpf_plan_release(p);
     delete res;
 }

@@ -114,7 +114,7 @@ class dpf_plan_desc(C.Structure):
 
 class dpf_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("wg_per_cu", C.c_int32), ("rows_per_item", C.c_int32),
-                ("lds_hash_bytes", C.c_int32), ("waves_per_wg", C.c_int32)]
+                ("lds_hash_bytes", C.c_int32), ("waves_per_wg", C.c_int32), ("max_workgroups", C.c_int32)]
 
 
 # Function table: name -> (restype, argtypes)
@@ -472,12 +472,13 @@ class Result:
 
 
 def execute(ctx: Context, plans: list, mode: str = "FUSED", wg_per_cu: int = 0, rows_per_item: int = 0,
-            lds_hash_bytes: int = -1, waves_per_wg: int = 0, stream=None) -> Result:
+            lds_hash_bytes: int = -1, waves_per_wg: int = 0, max_workgroups: int = 0,
+            stream=None) -> Result:
     """Enqueue plans (one fused launch, or the fragmented kernel sequence)."""
     lib = load()
     arr = (C.c_void_p * len(plans))(*[p.h.value for p in plans])
     o = dpf_exec_opts(DPF_MODE_FUSED if mode == "FUSED" else DPF_MODE_FRAGMENTED, wg_per_cu, rows_per_item,
-                      lds_hash_bytes, waves_per_wg)
+                      lds_hash_bytes, waves_per_wg, max_workgroups)
     h = C.c_void_p()
     _check(lib.dpf_execute(ctx.h, len(plans), C.cast(arr, C.c_void_p), C.byref(o), _stream_handle(stream),
                            C.byref(h)))

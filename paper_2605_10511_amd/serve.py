@@ -20,7 +20,10 @@ Tables larger than the residency budget are placed in pinned host memory
 mapped into the device and scanned over the host link (Section 3.1's zero
 copy path).  Requests on such tables run on a stream of their own and never
 share a batch with resident-table requests: a launch finishes when its
-slowest plan does, and a host-link scan takes tens of milliseconds.
+slowest plan does, and a host-link scan takes tens of milliseconds.  They
+also run with one workgroup per CU (``host_knobs``): the host link, not the
+CUs, bounds such a scan, and a full grid of persistent workgroups would hold
+every slot of every CU for the scan's whole duration.
 """
 from __future__ import annotations
 
@@ -54,7 +57,8 @@ class _Batch:
 
 class Server:
     def __init__(self, ctx: dpf.Context, db: dpf.Database, nstreams: int = 4, slots: int = 8,
-                 state_budget: int = 4 << 30, placements: dict | None = None, host_tables=()):
+                 state_budget: int = 4 << 30, placements: dict | None = None, host_tables=(),
+                 host_knobs: dict | None = None):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -67,8 +71,8 @@ class Server:
         self.hash_builds = 0
         self.hash_build_s = 0.0
         self.host_tables = set(host_tables)
-        if self.host_tables:
-            self.host_stream = torch.cuda.Stream()  # default priority
+        self.host_knobs = dict(host_knobs) if host_knobs is not None else {"max_workgroups": 64}
+        self.host_stream = torch.cuda.Stream() if self.host_tables else None  # default priority
 
     # -- preparation -------------------------------------------------------
     def _hash(self, pr: dict) -> dpf.Hash:
@@ -181,7 +185,7 @@ class Server:
                 b.reqs = [r]
                 b.footprint = r.footprint
                 r.issued = time.perf_counter() - t0
-                b.result = dpf.execute(self.ctx, [r.plan], stream=self.host_stream)
+                b.result = dpf.execute(self.ctx, [r.plan], stream=self.host_stream, **self.host_knobs)
                 b.event = torch.cuda.Event()
                 b.event.record(self.host_stream)
                 inflight.append(b)
@@ -204,14 +208,21 @@ class Server:
         for h in self.hashes.values():
             h.release()
         self.hashes.clear()
+        self.host_stream = None
 
 
 def latency_stats(done: list, seconds: float) -> dict:
     lat = np.array([(r.done - r.t) * 1e3 for r in done]) if done else np.zeros(0)
     out = {"completed": len(done), "qps": len(done) / seconds if seconds > 0 else 0.0}
     if len(lat):
+        wait = np.array([(r.issued - r.t) * 1e3 for r in done])
+        serv = np.array([(r.done - r.issued) * 1e3 for r in done])
         out.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                    "mean_ms": float(lat.mean()), "max_ms": float(lat.max())})
+                    "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                    "queue_wait_p50_ms": float(np.percentile(wait, 50)),
+                    "queue_wait_p99_ms": float(np.percentile(wait, 99)),
+                    "service_p50_ms": float(np.percentile(serv, 50)),
+                    "service_p99_ms": float(np.percentile(serv, 99))})
     for tmpl in ("FA", "SJ"):
         sel = np.array([(r.done - r.t) * 1e3 for r in done if r.template == tmpl])
         if len(sel):

@@ -270,3 +270,13 @@ def test_zone_decided_atoms(ctx, cut):
                 "aggs": [{"op": "COUNT"}, {"op": "SUM", "terms": [{"ref": {"col": "qty"}}]}]}
         G.say(f"zone cut {cut}: {f}")
         G.assert_same(G.run_gpu(db, spec), oracle.run(spec, t), f"zone {f}")
+
+
+@pytest.mark.parametrize("cap", [1, 3, 64])
+def test_grid_cap(ctx, cap):
+    """A capped grid (max_workgroups) drains the same work queue: same rows."""
+    t = {"fact": W.fa_table(300_000, seed=5)}
+    db = G.make_db(ctx, t, {"fact": W.FA_ENCODINGS})
+    spec = W.fa_query()
+    G.say(f"grid cap {cap}")
+    G.assert_same(G.run_gpu(db, spec, max_workgroups=cap), oracle.run(spec, t), f"cap {cap}")

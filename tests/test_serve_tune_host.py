@@ -43,6 +43,7 @@ def test_latency_stats():
     rs = []
     for i in range(200):
         r = serve.Request(i * 0.01, "FA" if i % 2 else "SJ", {}, "res")
+        r.issued = r.t + 0.0005
         r.done = r.t + 0.001 * (1 + (i % 100))
         rs.append(r)
     st = serve.latency_stats(rs, 2.0)
@@ -50,6 +51,8 @@ def test_latency_stats():
     lat = np.array([(r.done - r.t) * 1e3 for r in rs])
     assert st["p50_ms"] == np.percentile(lat, 50) and st["p99_ms"] == np.percentile(lat, 99)
     assert st["FA"]["n"] == 100 and st["SJ"]["n"] == 100
+    assert abs(st["queue_wait_p50_ms"] - 0.5) < 1e-9
+    assert abs(st["service_p50_ms"] + st["queue_wait_p50_ms"] - st["p50_ms"]) < 1e-6
     assert serve.latency_stats([], 1.0)["completed"] == 0
 
 
