@@ -221,11 +221,16 @@ __device__ __forceinline__ int64_t dict_value(CC& c, int64_t code, bool& ok) {
 __device__ __forceinline__ int zone_test(CC& c, CP& p, int m) {
     if (p.kind != PK_RANGE && p.kind != PK_NE) return -1;
     const MbHdr h = mb_hdr(c, m);
-    if (!h.ok || h.b > 40) return -1;
-    const __int128 span = (h.b ? (((__int128)1) << h.b) - 1 : 0);
-    __int128 lo = h.base, hi = h.base;
+    // int64 is exact here: |base| < 2^61, width <= 32, |dmin| < 2^31, so the
+    // interval ends stay below 2^62 in magnitude.  Otherwise: undecided.
+    const int64_t kLim = int64_t(1) << 61;
+    if (!h.ok || h.b > 32 || h.base >= kLim || h.base <= -kLim) return -1;
+    const int64_t span = h.b ? (int64_t)((uint64_t(1) << h.b) - 1) : 0;
+    int64_t lo = h.base, hi = h.base;
     if (c.enc == ENC_DELTA) {
-        const __int128 d = (__int128)ro(c.dmin)[m] * (kMB - 1);
+        const int64_t dmin = ro(c.dmin)[m];
+        if (dmin >= (int64_t(1) << 31) || dmin <= -(int64_t(1) << 31)) return -1;
+        const int64_t d = dmin * (kMB - 1);
         if (d < 0) lo += d; else hi += d;
         hi += span * (kMB - 1);
     } else {
@@ -525,20 +530,15 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     cptr<uint8_t> hs = ro(c.heap + S.h0);
     const uint32_t total_b = (uint32_t)(S.h1 - S.h0);
     int nrec = 0;
-    Seg nxt;
-    for (uint32_t base = 0;; base += kSegIters * kWave) {
-        // Double buffering: the next segment's loads are in flight while
-        // this one is compared.
-        const bool more = base + kSegIters * kWave < nvec;
-        if (more) load_segment(nxt, S, base + kSegIters * kWave, nvec, lane);
-        // Hot loop.  A word whose 4-byte windows match a prefix is queued
-        // with its two successors in LDS (a rare, wave-uniform branch).
+    // Hot loop over one segment.  A word whose 4-byte windows match a prefix
+    // is queued with its two successors in LDS (a rare, wave-uniform branch).
+    auto scan = [&](const Seg& G, uint32_t base) {
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
             if (base + (uint32_t)it * kWave > nvec) break;  // slots past the mini block hold zeros
-            const uint4 w = S.cur.W[it];
+            const uint4 w = G.W[it];
             uint32_t nx, nx2;
-            next_words(S.cur, it, lane, nx, nx2);
+            next_words(G, it, lane, nx, nx2);
             const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
             const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
 #pragma unroll
@@ -566,8 +566,20 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
                 }
             }
         }
-        if (!more) break;
-        S.cur = nxt;
+    };
+    // Two segment buffers in turn: the next segment's loads are in flight
+    // while the current one is compared.
+    constexpr uint32_t kSeg = kSegIters * kWave;
+    Seg other;
+    for (uint32_t base = 0;; base += 2 * kSeg) {
+        const bool more1 = base + kSeg < nvec;
+        if (more1) load_segment(other, S, base + kSeg, nvec, lane);
+        scan(S.cur, base);
+        if (!more1) break;
+        const bool more2 = base + 2 * kSeg < nvec;
+        if (more2) load_segment(S.cur, S, base + 2 * kSeg, nvec, lane);
+        scan(other, base + kSeg);
+        if (!more2) break;
     }
     if (nrec) drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
     wave_lds_sync();
@@ -1044,7 +1056,7 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
 template <int NW, bool kStr>
-__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr ? 5 : 4, 8))) void fused_kernel(BatchArgs a) {
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr ? 6 : 4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
     uint8_t* shared_area = smem + 64;

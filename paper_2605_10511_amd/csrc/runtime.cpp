@@ -722,7 +722,7 @@ constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
 constexpr int64_t kDefaultMbPerItem = 64;  // 16,384 rows
-constexpr int kTargetWavesPerCU = 32;       // string stage: 5 waves per SIMD resident, the rest queued
+constexpr int kTargetWavesPerCU = 32;       // string stage: 6 waves per SIMD resident, the rest queued
                                             // (measured fastest: smaller items, no idle tail)
 constexpr int kTargetWavesPerCUNoStr = 28;  // without it: 7 waves per SIMD
 
