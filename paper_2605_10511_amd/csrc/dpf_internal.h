@@ -83,7 +83,20 @@ struct DevHash {
     int32_t pay64[2];   // payload k stored as int64 (else int32)
     int32_t lds_off;    // >= 0: byte offset of the workgroup's LDS copy
     uint32_t bytes;     // keys + payloads
+    // Two-hash bit filter over the keys (small tables only): a probe of a
+    // table left in HBM first tests the workgroup's LDS copy of the filter.
+    const uint32_t* filt;  // nullptr: none
+    int32_t flog2;         // filter bits = 2^flog2
+    int32_t filt_lds_off;  // >= 0: byte offset of the LDS copy
+    int32_t bits_lds_off;  // >= 0: byte offset of an LDS copy of the bitmap
 };
+constexpr int kMaxFilterLog2 = 18;  // 32 KB
+__host__ __device__ inline uint32_t filter_bit(int32_t key, int flog2) {
+    return ((uint32_t)key * 0x2545F491u) >> (32 - flog2);
+}
+__host__ __device__ inline uint32_t filter_bit2(int32_t key, int flog2) {
+    return ((uint32_t)key * 0x9E3779B1u + 0x7F4A7C15u) >> (32 - flog2);
+}
 
 struct DevProbe {
     int32_t fk_col;
@@ -162,6 +175,9 @@ struct HashBuildArgs {
     int32_t log2cap;
     uint32_t* bits;     // membership bitmap (nullptr: none)
     int64_t bmin;
+    uint32_t* filt;     // bit filter (nullptr: none)
+    int32_t flog2;
+    int32_t pad2;
 };
 
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.

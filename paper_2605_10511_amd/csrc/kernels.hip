@@ -651,11 +651,22 @@ __device__ __forceinline__ int hash_find(CH& h, const uint8_t* smem_shared, int6
     return -1;
 }
 
+// LDS filter test: false means the key is certainly absent.
+__device__ __forceinline__ bool filter_maybe(CH& h, const uint8_t* smem_shared, int64_t key) {
+    if (h.filt_lds_off < 0) return true;
+    const uint32_t b = filter_bit((int32_t)key, h.flog2), b2 = filter_bit2((int32_t)key, h.flog2);
+    const uint32_t* f = reinterpret_cast<const uint32_t*>(smem_shared + h.filt_lds_off);
+    return ((f[b >> 5] >> (b & 31)) & (f[b2 >> 5] >> (b2 & 31)) & 1u) != 0;
+}
+
 // Key-range bitmap test (the table has one: h.bits != nullptr).
-__device__ __forceinline__ bool bitmap_has(CH& h, int64_t key) {
+__device__ __forceinline__ bool bitmap_has(CH& h, const uint8_t* smem_shared, int64_t key) {
     const uint64_t d = (uint64_t)key - (uint64_t)h.bmin;
     if (d >= h.bspan) return false;
-    return (ro(h.bits)[d >> 5] >> (d & 31)) & 1u;
+    const uint32_t w = h.bits_lds_off >= 0
+                           ? reinterpret_cast<const uint32_t*>(smem_shared + h.bits_lds_off)[d >> 5]
+                           : ro(h.bits)[d >> 5];
+    return (w >> (d & 31)) & 1u;
 }
 
 // Membership of the lane's four keys (mask bit k: row 64 k + lane is live):
@@ -664,10 +675,17 @@ __device__ __forceinline__ bool bitmap_has(CH& h, int64_t key) {
 template <bool kLds>
 __device__ __forceinline__ uint32_t hash_member4(CH& h, const uint8_t* smem_shared, const int64_t key[4],
                                                  uint32_t live) {
+    if (h.filt_lds_off >= 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (key[k] < INT32_MIN || key[k] > INT32_MAX || !filter_maybe(h, smem_shared, key[k])) live &= ~(1u << k);
+        if (__ballot(live != 0) == 0) return 0;
+    }
     if (h.bits) {
         uint32_t found = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) found |= (uint32_t)(((live >> k) & 1u) && bitmap_has(h, key[k])) << k;
+        for (int k = 0; k < 4; ++k)
+            found |= (uint32_t)(((live >> k) & 1u) && bitmap_has(h, smem_shared, key[k])) << k;
         return found;
     }
     const int32_t* lkeys = reinterpret_cast<const int32_t*>(smem_shared + h.lds_off);
@@ -764,8 +782,12 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv
             CC& fc = Q.cols[P.fk_col];
             int64_t fk = decode_at(fc, m, i, ok_hdr);
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, ok_hdr);
+            if (fk < INT32_MIN || fk > INT32_MAX || !filter_maybe(P.h, smem_shared, fk)) {
+                ok = false;  // certainly absent
+                continue;
+            }
             if (P.h.bits && P.pay_slot[0] < 0 && P.pay_slot[1] < 0) {
-                ok = bitmap_has(P.h, fk);  // membership only
+                ok = bitmap_has(P.h, smem_shared, fk);  // membership only
                 continue;
             }
             const bool lds = P.h.lds_off >= 0;
@@ -966,6 +988,18 @@ __device__ unsigned long long flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
 __device__ void load_lds_state(CQ& Q, uint8_t* smem_shared) {
     for (int j = 0; j < Q.nprobes; ++j) {
         CH& h = Q.probes[j].h;
+        if (h.bits_lds_off >= 0) {
+            cptr<uint4> src = (cptr<uint4>)h.bits;
+            uint4* dst = reinterpret_cast<uint4*>(smem_shared + h.bits_lds_off);
+            const uint32_t n = (uint32_t)((h.bspan + 127) / 128);  // 16-byte units
+            for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = ld4(src, e);
+        }
+        if (h.filt_lds_off >= 0) {
+            cptr<uint4> src = (cptr<uint4>)h.filt;
+            uint4* dst = reinterpret_cast<uint4*>(smem_shared + h.filt_lds_off);
+            const uint32_t n = (1u << h.flog2) / 128u;  // 16-byte units
+            for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = ld4(src, e);
+        }
         if (h.lds_off < 0) continue;
         cptr<uint4> src = (cptr<uint4>)h.keys;
         uint4* dst = reinterpret_cast<uint4*>(smem_shared + h.lds_off);
@@ -1211,6 +1245,11 @@ __global__ __launch_bounds__(kBlock) void hash_insert_kernel(const HashBuildArgs
                     if (A.bits) {
                         const uint64_t d = (uint64_t)(key[k] - A.bmin);
                         atomicOr(&A.bits[d >> 5], 1u << (d & 31));
+                    }
+                    if (A.filt) {
+                        const uint32_t fb = filter_bit(kk, A.flog2), fb2 = filter_bit2(kk, A.flog2);
+                        atomicOr(&A.filt[fb >> 5], 1u << (fb & 31));
+                        atomicOr(&A.filt[fb2 >> 5], 1u << (fb2 & 31));
                     }
                     for (int j = 0; j < A.npay; ++j) {
                         if (A.pay64[j]) reinterpret_cast<int64_t*>(A.pay[j])[s] = pay[j][k];

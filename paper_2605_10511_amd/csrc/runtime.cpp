@@ -634,8 +634,17 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     const uint64_t kspan = count ? (uint64_t)(mm[1] - mm[0]) + 1 : 0;
     const bool use_bits = count && (uint64_t)(mm[1] - mm[0]) < kMaxBitmapBits;
     const size_t bits_off = align_up(bytes, 256);
-    const size_t bits_words = use_bits ? (size_t)((kspan + 31) / 32) : 0;
-    const size_t alloc_bytes = use_bits ? bits_off + bits_words * 4 : bytes;
+    const size_t bits_words = use_bits ? (size_t)((kspan + 127) / 128) * 4 : 0;  // whole 16-byte units
+    // LDS bit filter for small tables: two hashes, ~128 bits per key (a
+    // false-positive rate near 1e-4), at most 2^kMaxFilterLog2 bits
+    int flog2 = 0;
+    if (count && count <= (uint64_t(1) << kMaxFilterLog2) / 16) {
+        flog2 = 12;
+        while (flog2 < kMaxFilterLog2 && (uint64_t(1) << flog2) < count * 128) ++flog2;
+    }
+    const size_t filt_off = align_up(use_bits ? bits_off + bits_words * 4 : bytes, 256);
+    const size_t filt_words = flog2 ? (size_t(1) << flog2) / 32 : 0;
+    const size_t alloc_bytes = flog2 ? filt_off + filt_words * 4 : (use_bits ? bits_off + bits_words * 4 : bytes);
     dpf_hash h = new (std::nothrow) dpf_hash_s();
     if (!h) return fail(DPF_ERR_OOM, "hash");
     h->ctx = ctx;
@@ -661,6 +670,9 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     A.bmin = use_bits ? mm[0] : 0;
     hipError_t e = launch_fill_i32((int32_t*)h->mem, kEmptyKey, (int64_t)cap, s);
     if (e == hipSuccess && use_bits) e = launch_fill_i32((int32_t*)A.bits, 0, (int64_t)bits_words, s);
+    A.filt = flog2 ? (uint32_t*)((uint8_t*)h->mem + filt_off) : nullptr;
+    A.flog2 = flog2;
+    if (e == hipSuccess && flog2) e = launch_fill_i32((int32_t*)A.filt, 0, (int64_t)filt_words, s);
     if (e == hipSuccess) e = hipMemcpyAsync(scratch + args_off, &A, sizeof A, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_hash_insert((const HashBuildArgs*)(scratch + args_off), grid, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&status, A.status, 4, hipMemcpyDeviceToHost, s);
@@ -684,6 +696,10 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     d.bits = A.bits;
     d.bmin = A.bmin;
     d.bspan = use_bits ? kspan : 0;
+    d.filt = A.filt;
+    d.flog2 = flog2;
+    d.filt_lds_off = -1;
+    d.bits_lds_off = -1;
     dpf_hash_stats& st = h->stats;
     st.entries = (int64_t)count;
     st.capacity = (int64_t)cap;
@@ -732,9 +748,23 @@ void assign_lds(dpf_plan p, int32_t budget) {
     DevQuery& q = p->hq;
     if (budget < 0) budget = kDefaultLdsHash;
     std::vector<int> order;
+    int32_t off = 0;
+    // A probe that needs no payload only asks membership: its key-range
+    // bitmap (when it has one) is the structure placed in LDS.
     for (int j = 0; j < q.nprobes; ++j) {
-        q.probes[j].h.lds_off = -1;
-        if (p->hash_place[j] != DPF_HASH_HBM) order.push_back(j);
+        DevProbe& P = q.probes[j];
+        P.h.lds_off = -1;
+        P.h.bits_lds_off = -1;
+        if (p->hash_place[j] == DPF_HASH_HBM) continue;
+        if (P.h.bits && P.pay_slot[0] < 0 && P.pay_slot[1] < 0) {
+            const int32_t b = (int32_t)align_up((size_t)((P.h.bspan + 127) / 128) * 16, 16);
+            if (off + (int64_t)b <= budget) {
+                P.h.bits_lds_off = off;
+                off += b;
+                continue;
+            }
+        }
+        order.push_back(j);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         // explicit LDS requests first, then smallest first
@@ -742,12 +772,21 @@ void assign_lds(dpf_plan p, int32_t budget) {
         if (ra != rb) return ra < rb;
         return q.probes[a].h.bytes < q.probes[b].h.bytes;
     });
-    int32_t off = 0;
     for (int j : order) {
         uint32_t b = q.probes[j].h.bytes;
         if (off + (int64_t)b > budget) continue;
         q.probes[j].h.lds_off = off;
         off += (int32_t)align_up(b, 16);
+    }
+    // bit filters of the tables that stay in HBM, in probe order
+    for (int j = 0; j < q.nprobes; ++j) {
+        DevHash& h = q.probes[j].h;
+        h.filt_lds_off = -1;
+        if (!h.filt || h.lds_off >= 0 || h.bits_lds_off >= 0) continue;
+        const int32_t b = (int32_t)((size_t(1) << h.flog2) / 8);
+        if (off + (int64_t)b > budget) continue;
+        h.filt_lds_off = off;
+        off += (int32_t)align_up((size_t)b, 16);
     }
     const int64_t aggb = q.ngroups * q.nacc * 8;
     q.agg_lds = aggb <= kAggLdsMax;
