@@ -326,17 +326,19 @@ def bench_mix(args):
     def frag():
         return [dpf.execute(ctx, [p], mode="FRAGMENTED") for p in plans]
 
+    # Every execution of a plan writes the plan's one result buffer: each
+    # mode's rows are read right after that mode ran.
     l0 = ctx.info().launches
     bms, bwall, bres = timed(batch, args.steps)
     blaunch = (ctx.info().launches - l0) / (args.steps + 1)
+    got_b = [bres.get(i) for i in range(len(plans))]
+    bres.release()
     dms, _, dres = timed(batch_default, args.steps)
     dres.release()
     sms, swall, sres = timed(solo, max(1, args.steps // 4))
-    fms, fwall, fres = timed(frag, 1)
-    got_b = [bres.get(i) for i in range(len(plans))]
     got_s = [r.get(0) for r in sres]
+    fms, fwall, fres = timed(frag, 1)
     got_f = [r.get(0) for r in fres]
-    bres.release()
     for r in sres + fres:
         r.release()
     batch_eq_solo = all(np.array_equal(a, b) for a, b in zip(got_b, got_s))
@@ -352,7 +354,12 @@ def bench_mix(args):
         with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
             want = list(ex.map(lambda sp: oracle.run(sp, tables), specs))
         ot = time.perf_counter() - t2
-        parity = all(np.array_equal(w, g) for w, g in zip(want, got_b))
+        bad = [i for i, (w, g) in enumerate(zip(want, got_b)) if not np.array_equal(w, g)]
+        parity = not bad
+        for i in bad[:4]:
+            again = oracle.run(specs[i], tables)  # single-threaded recomputation
+            log(f"[mix] query {i} ({M['queries'][i][0]} on table {M['queries'][i][1]}) differs: single-thread "
+                f"oracle == gpu {np.array_equal(again, got_b[i])}, == threaded oracle {np.array_equal(again, want[i])}")
         cpu = {"value": tot_rows / ot, "unit": "rows/s", "cores": min(16, os.cpu_count() or 1),
                "kind": "oracle", "sample": f"all 64 queries of the mix ({tot_rows:,} query rows), one "
                                            f"oracle call per query on a thread pool ({ot:.1f} s)"}

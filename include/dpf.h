@@ -318,9 +318,11 @@ dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_
  * synchronises the stream).  Rows are int64: group key values, then the
  * aggregate columns, one row per non-empty group, ascending by key.  Returns
  * the device-reported status (e.g. DPF_ERR_CAPACITY, DPF_ERR_CORRUPT) and no
- * rows when the kernel reported an error.  Each call decodes the buffer anew
- * (so a result captured in a graph can be read after every replay); *rows
- * stays valid until the next call on the same result or its release. */
+ * rows when the kernel reported an error.  The records live in the plan's
+ * one pinned result buffer, which every execution of that plan overwrites:
+ * read a result before the plan runs again.  Each call decodes the buffer
+ * anew (so a result captured in a graph can be read after every replay);
+ * *rows stays valid until the next call on the same result or its release. */
 dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* ncols,
                           const int64_t** rows);
 /* Waits for the execution to finish (its completion event; a captured

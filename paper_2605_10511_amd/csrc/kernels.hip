@@ -160,19 +160,44 @@ __device__ __forceinline__ MbHdr mb_hdr(CC& c, int m) {
 // Dense decode of the wave's four rows (64k + lane) of mini block m.
 // DICT columns yield codes; VARLEN yields lengths.  Returns false on a
 // corrupt header.
-__device__ __forceinline__ bool decode_dense(CC& c, int m, int lane, int64_t v[4]) {
-    MbHdr h = mb_hdr(c, m);
-    uint64_t u[4];
-    if (h.b == 0) {
+// Dense decode in two steps, so that a wave can have the loads of several
+// mini blocks in flight: issue_dense reads the header and the packed words
+// (raw 64-bit windows, or the full values for widths above 32), and
+// finish_dense unpacks them (DELTA: a wave scan).
+struct RawDense {
+    MbHdr h;
+    int64_t dmin;
+    uint64_t raw[4];
+    uint32_t sh[4];
+};
+
+__device__ __forceinline__ void issue_dense(CC& c, int m, int lane, RawDense& R) {
+    R.h = mb_hdr(c, m);
+    R.dmin = c.enc == ENC_DELTA ? ro(c.dmin)[m] : 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = 0;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = bits_at(h.w, (uint32_t)(64 * k + lane) * (uint32_t)h.b, h.b);
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t bitpos = (uint32_t)(64 * k + lane) * (uint32_t)R.h.b;
+        R.sh[k] = bitpos & 31u;
+        if (R.h.b == 0) {
+            R.raw[k] = 0;
+        } else if (R.h.b <= 32) {
+            R.raw[k] = *(cptr<u64_a4>)(R.h.w + (bitpos >> 5));
+        } else {
+            R.raw[k] = bits_at(R.h.w, bitpos, R.h.b);
+            R.sh[k] = 0;
+        }
     }
+}
+
+__device__ __forceinline__ bool finish_dense(CC& c, const RawDense& R, int lane, int64_t v[4]) {
+    const MbHdr& h = R.h;
+    uint64_t u[4];
+    const uint64_t mask = h.b >= 64 ? ~uint64_t(0) : ((uint64_t(1) << h.b) - 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = h.b == 0 ? 0 : ((R.raw[k] >> R.sh[k]) & mask);
     if (c.enc == ENC_DELTA) {
         // value_i = anchor + i * dmin + sum_{j <= i} packed_j  (packed_0 = 0)
-        uint64_t dmin = (uint64_t)ro(c.dmin)[m];
+        const uint64_t dmin = (uint64_t)R.dmin;
         uint64_t carry = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -186,6 +211,12 @@ __device__ __forceinline__ bool decode_dense(CC& c, int m, int lane, int64_t v[4
         for (int k = 0; k < 4; ++k) v[k] = (int64_t)((uint64_t)h.base + u[k]);
     }
     return h.ok;
+}
+
+__device__ __forceinline__ bool decode_dense(CC& c, int m, int lane, int64_t v[4]) {
+    RawDense R;
+    issue_dense(c, m, lane, R);
+    return finish_dense(c, R, lane, v);
 }
 
 // Value of row i of mini block m (random access).  DELTA sums the packed
@@ -846,6 +877,20 @@ __device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, const
     wave_lds_sync();
 }
 
+__device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int64_t row0,
+                                                uint32_t mask, int lane, int& npend, bool& ok_hdr) {
+    if (__ballot(mask != 0) == 0) return;
+    // Queue survivors (wave ballot + mbcnt compaction).
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        bool bit = (mask >> k) & 1u;
+        uint64_t b = __ballot(bit);
+        if (bit) W.pend[npend + bits_below(b)] = (uint32_t)(row0 + 64 * k + lane);
+        npend += (int)__popcll(b);
+    }
+    if (npend >= kWave) flush_pending(Q, smem_shared, W, npend, lane, ok_hdr);
+}
+
 // Stage A of mini block m: returns the mask of rows passing every atom (row
 // 64 k + lane -> bit k).  kEager: the plan's one string atom comes last and
 // its loads are issued before the integer atoms run, so both wait for memory
@@ -910,40 +955,53 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
         }
         return;
     }
-    uint32_t mask;
-    if (npreds == 0) {
-        // No fact predicate: the first (most selective) probe filters as a
-        // semi-join over the dense foreign keys; its survivors are probed
-        // again, with payloads, in stage B.
-        mask = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
-        CPR& P0 = Q.probes[0];
-        CC& fc = Q.cols[P0.fk_col];
-        int64_t fk[4];
-        ok_hdr &= decode_dense(fc, m, lane, fk);
-        if (fc.enc == ENC_DICT)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
-        mask = P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
-                                 : hash_member4<false>(P0.h, smem_shared, fk, mask);
-    } else {
-        mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
-                   ? (kStr ? filter_tile<true, kStr>(Q, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
-                   : filter_tile<false, kStr>(Q, W, m, lane, nvalid, ok_hdr);
-    }
-    if (__ballot(mask != 0) == 0) return;
-
-    // Queue survivors (wave ballot + mbcnt compaction).
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        bool bit = (mask >> k) & 1u;
-        uint64_t b = __ballot(bit);
-        if (bit) W.pend[npend + bits_below(b)] = (uint32_t)(row0 + 64 * k + lane);
-        npend += (int)__popcll(b);
-    }
-    if (npend >= kWave) flush_pending(Q, smem_shared, W, npend, lane, ok_hdr);
+    if (npreds == 0) return;  // probes without predicates: semi_tiles handles those plans
+    const uint32_t mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
+                              ? (kStr ? filter_tile<true, kStr>(Q, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
+                              : filter_tile<false, kStr>(Q, W, m, lane, nvalid, ok_hdr);
+    queue_survivors(Q, smem_shared, W, row0, mask, lane, npend, ok_hdr);
 }
+
+// Semi-join stage A of one mini block whose foreign keys issue_dense read:
+// the first (most selective) probe filters; its survivors are probed again,
+// with payloads, in stage B.
+__device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
+                                          const RawDense& R, int& npend, bool& ok_hdr) {
+    const int64_t row0 = (int64_t)m * kMB;
+    const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
+    CPR& P0 = Q.probes[0];
+    CC& fc = Q.cols[P0.fk_col];
+    int64_t fk[4];
+    ok_hdr &= finish_dense(fc, R, lane, fk);
+    if (fc.enc == ENC_DICT)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
+    mask = P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
+                             : hash_member4<false>(P0.h, smem_shared, fk, mask);
+    queue_survivors(Q, smem_shared, W, row0, mask, lane, npend, ok_hdr);
+}
+
+// The semi-join tiles m0, m0 + NW, ... < m1 of one wave, two in flight: the
+// next tile's keys are loaded while the current one is probed.
+template <int NW>
+__device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m0, int m1,
+                                           int lane, int& npend, bool& ok_hdr) {
+    CC& fc = Q.cols[Q.probes[0].fk_col];
+    RawDense A, B;
+    if (m0 < m1) issue_dense(fc, m0, lane, A);
+    for (int m = m0; m < m1; m += 2 * NW) {
+        const int m2 = m + NW;
+        if (m2 < m1) issue_dense(fc, m2, lane, B);
+        semi_tile(Q, smem_shared, W, m, lane, A, npend, ok_hdr);
+        if (m2 >= m1) break;
+        if (m2 + NW < m1) issue_dense(fc, m2 + NW, lane, A);
+        semi_tile(Q, smem_shared, W, m2, lane, B, npend, ok_hdr);
+    }
+}
+
 
 // Per-wave LDS: (plans with fact predicates) the survivor queue, then one
 // region shared by the stage-B value slots and the string predicate's row
@@ -1134,7 +1192,10 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
         }
         const int mb0 = (item - a.item_start[qi]) * a.mb_per_item;
         const int mb1 = min(mb0 + a.mb_per_item, Q.nmb);
-        for (int m = mb0 + wave; m < mb1; m += NW) process_tile<kStr>(Q, shared_area, W, m, lane, npend, ok_hdr);
+        if (Q.npreds == 0 && Q.nprobes > 0)
+            semi_tiles<NW>(Q, shared_area, W, mb0 + wave, mb1, lane, npend, ok_hdr);
+        else
+            for (int m = mb0 + wave; m < mb1; m += NW) process_tile<kStr>(Q, shared_area, W, m, lane, npend, ok_hdr);
         if (npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
@@ -1191,7 +1252,7 @@ __device__ __forceinline__ uint32_t hash_tile_mask(CHB& A, int m, int lane, int 
 __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs* __restrict__ args) {
     CHB& A = *ro(args);
     const int lane = lane_id();
-    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int gw = uniform_i32((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));  // wave-uniform
     const int nw = (gridDim.x * blockDim.x) >> 6;
     bool ok = true;
     unsigned long long cnt = 0;
@@ -1222,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void hash_count_kernel(const HashBuildArgs*
 __global__ __launch_bounds__(kBlock) void hash_insert_kernel(const HashBuildArgs* __restrict__ args) {
     CHB& A = *ro(args);
     const int lane = lane_id();
-    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int gw = uniform_i32((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));  // wave-uniform
     const int nw = (gridDim.x * blockDim.x) >> 6;
     bool ok = true;
     uint32_t flags = 0;
@@ -1282,7 +1343,7 @@ __global__ __launch_bounds__(kBlock) void frag_decode_int(const DevQuery* __rest
     CQ& Q = *ro(q);
     CC& C = Q.cols[c];
     const int lane = lane_id();
-    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int gw = uniform_i32((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));  // wave-uniform
     const int nw = (gridDim.x * blockDim.x) >> 6;
     bool ok = true;
     for (int m = gw; m < Q.nmb; m += nw) {
@@ -1302,7 +1363,7 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
     CQ& Q = *ro(q);
     CC& C = Q.cols[c];
     const int lane = lane_id();
-    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int gw = uniform_i32((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));  // wave-uniform
     const int nw = (gridDim.x * blockDim.x) >> 6;
     bool ok = true;
     for (int m = gw; m < Q.nmb; m += nw) {

@@ -280,3 +280,18 @@ def test_grid_cap(ctx, cap):
     spec = W.fa_query()
     G.say(f"grid cap {cap}")
     G.assert_same(G.run_gpu(db, spec, max_workgroups=cap), oracle.run(spec, t), f"cap {cap}")
+
+
+@pytest.mark.parametrize("mode", ["FUSED", "FRAGMENTED"])
+def test_delta_cuts_every_path(ctx, mode):
+    """A sorted DELTA column cut at many points, by every execution path: the
+    fragmented kernels decode every mini block (no header shortcut), the
+    fused one decodes the blocks the header does not settle."""
+    t = {"fact": W.fa_table(1_300_000, seed=400)}
+    db = G.make_db(ctx, t, {"fact": W.FA_ENCODINGS})
+    for c in (100, 1500, 1882, 2203, 2555):
+        spec = {"fact": "fact", "filters": [{"col": "date", "op": "LT", "value": c}], "probes": [],
+                "group_by": [{"col": "flagA"}],
+                "aggs": [{"op": "COUNT"}, {"op": "SUM", "terms": [{"ref": {"col": "date"}}]}]}
+        G.say(f"{mode} date < {c}")
+        G.assert_same(G.run_gpu(db, spec, mode=mode), oracle.run(spec, t), f"{mode} date < {c}")

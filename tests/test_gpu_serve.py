@@ -37,13 +37,16 @@ def test_tuner_picks_a_measured_point(env, tmp_path):
     again = tune.tune(ctx, plans, grid=grid, cache=cache)
     assert again["best"] == e["best"] and again["key"] == e["key"]
     import torch
+    # a plan's executions share its result buffer: read each before the next
     r1 = dpf.execute(ctx, plans, **e["best"])
+    torch.cuda.synchronize()
+    tuned = [r1.get(i) for i in range(len(specs))]
+    r1.release()
     r2 = dpf.execute(ctx, plans)
     torch.cuda.synchronize()
     for i, s in enumerate(specs):
-        G.assert_same(r1.get(i), oracle.run(s, tables), f"tuned plan {i}")
-        G.assert_same(r2.get(i), r1.get(i), f"default plan {i}")
-    r1.release()
+        G.assert_same(tuned[i], oracle.run(s, tables), f"tuned plan {i}")
+        G.assert_same(r2.get(i), tuned[i], f"default plan {i}")
     r2.release()
     for p in plans:
         p.release()
