@@ -1200,6 +1200,8 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         }
         if (items > INT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "too many work items; raise rows_per_item");
         a.item_start[n] = (int32_t)items;
+        // no more workgroups than items: an idle workgroup still claims and signs off
+        grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, items));
         HIP_TRY(launch_fused(a, waves, grid, lds, s));
         ctx->launches++;
     } else {
