@@ -25,7 +25,6 @@ constexpr int kMaxBatch = 64;     // plans per fused launch
 constexpr int kMaxHashCols = 8;   // dimension columns per hash build
 constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
 constexpr int64_t kMaxGroups = int64_t(1) << 22;  // direct-indexed group table limit
-constexpr int kStrHeapCap = 11264;  // per-wave LDS bytes staging one mini block's strings
 constexpr int32_t kEmptyKey = INT32_MIN;
 constexpr int kXcds = 8;             // XCDs per device; workgroup i is dispatched to XCD i % 8
 constexpr int kCounterStride = 32;   // 32-bit words between work-queue counters (128-byte lines)
@@ -147,7 +146,7 @@ struct BatchArgs {
                           // its finished workgroups (line 8 + x); finished XCDs (line 16)
     int32_t lds_shared;   // max lds_shared over the batch
     int32_t str_stage;    // per-wave string staging present
-    int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate)
+    int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate or a probe)
 };
 
 // Hash build over a dimension table.

@@ -308,18 +308,20 @@ __device__ __forceinline__ uint32_t eval_int_pred(CP& p, cptr<int64_t> in_vals,
 // String predicate "s1 then s2" (LIKE '%s1%s2%', paper Section 4.1) over one
 // mini block, byte-parallel.
 //
-// The mini block's heap is read into registers with 16-byte loads: each lane
-// holds four consecutive words, and the two words after them come from the
-// next lane by a lane shift.  At every byte position the 4-byte window is
-// compared with the first 4 bytes of s1 and of s2 (three byte-aligns and
-// eight compares per word; the hit masks combine in scalar registers), so a
-// chance match costs nothing until a whole 4-byte prefix agrees.  The rare
-// hits are checked against 8 bytes taken from the same registers (the rest
-// of a longer word from memory), queued, mapped to their row by binary
-// search over the row offsets (LDS), and kept as the row's leftmost s1 start
-// and rightmost s2 start.  A row matches iff rightmost s2 >= leftmost s1 +
-// |s1|: the leftmost s1 leaves the most room for s2, the rightmost s2 is the
-// likeliest to follow it.
+// The mini block's heap is read into registers in 2 KB segments of 16-byte
+// loads, two segments in turn (the next one loads while the current one is
+// compared): each lane holds four consecutive words, and the two words after
+// them come from the next lane by a DPP lane shift.  At every byte position
+// the 4-byte window is compared with the first 4 bytes of s1 and of s2
+// (three byte-aligns and eight compares per word; the hit masks combine in
+// scalar registers), so a chance match costs nothing until a whole 4-byte
+// prefix agrees.  A word with such a hit is queued in LDS with its two
+// successors; after the last segment the queued words are checked together,
+// one per lane, against 8-byte windows (the rest of a longer pattern from
+// memory), mapped to their row by binary search over the row offsets (LDS),
+// and kept as the row's leftmost s1 start and rightmost s2 start.  A row
+// contains s1 then s2 iff some s2 start b and s1 start a satisfy b >= a +
+// |s1|, that is iff rightmost s2 >= leftmost s1 + |s1|.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int row_of(const uint32_t* offs, uint32_t p) {
     int lo = 0, hi = 255;  // largest r with offs[r] <= p
@@ -549,8 +551,12 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
         ov.z = ov.y + len[1];
         ov.w = ov.z + len[2];
         reinterpret_cast<uint4*>(offs)[lane] = ov;
-        reinterpret_cast<uint4*>(L.first1)[lane] = make_uint4(~0u, ~0u, ~0u, ~0u);
-        reinterpret_cast<uint4*>(L.last2)[lane] = make_uint4(0u, 0u, 0u, 0u);
+        // Materialised here (the empty asm keeps the compiler from hoisting
+        // the constant registers out of the tile loop, where they spilled).
+        uint32_t ones = ~0u, zero = 0u;
+        asm volatile("" : "+v"(ones), "+v"(zero));
+        reinterpret_cast<uint4*>(L.first1)[lane] = make_uint4(ones, ones, ones, ones);
+        reinterpret_cast<uint4*>(L.last2)[lane] = make_uint4(zero, zero, zero, zero);
     }
     if (lane == 0) offs[256] = total;
     if ((uint64_t)total != S.h1 - S.h0) { ok = false; return 0; }
