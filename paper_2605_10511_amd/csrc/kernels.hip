@@ -76,6 +76,7 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
 // row is masked off, receives 0.
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
 constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1
+constexpr int kDppWaveShr1 = 0x138;  // lane i receives lane i - 1
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
 
 template <int kCtrl, int kRowMask = 0xf>
@@ -211,6 +212,12 @@ __device__ __forceinline__ bool finish_dense(CC& c, const RawDense& R, int lane,
         for (int k = 0; k < 4; ++k) v[k] = (int64_t)((uint64_t)h.base + u[k]);
     }
     return h.ok;
+}
+
+// An empty use of R's packed words: their loads must be complete here.
+__device__ __forceinline__ void dense_ready(const RawDense& R) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) asm volatile("" ::"v"(R.raw[k]));
 }
 
 __device__ __forceinline__ bool decode_dense(CC& c, int m, int lane, int64_t v[4]) {
@@ -494,6 +501,14 @@ __device__ __forceinline__ void str_begin(CC& c, int m, int lane, StrTile& S) {
     }
 }
 
+// An empty use of every word of G: the loads that fill G must be complete
+// here, so the compares that follow need no wait of their own.
+__device__ __forceinline__ void seg_ready(const Seg& G) {
+#pragma unroll
+    for (int it = 0; it < kSegIters; ++it)
+        asm volatile("" ::"v"(G.W[it].x), "v"(G.W[it].y), "v"(G.W[it].z), "v"(G.W[it].w));
+}
+
 // Neighbour words of lane's segment slot it: the next lane's first two words
 // (for lane 63, those of the next slot's lane 0, or the words after the
 // segment).
@@ -521,10 +536,23 @@ __device__ __forceinline__ void drain_records(const StrLds& L, int nrec, uint32_
     wave_lds_sync();
 }
 
+// Scan modes of the string test, by the shorter word's length n:
+//   kStrMasked  (n < 4):  4-byte windows at every byte, masked to n bytes;
+//   kStrShifted (n < 7):  4-byte windows at every byte (three byte-aligns a word);
+//   kStrAligned (n >= 7): every occurrence covers a whole 4-byte-aligned word,
+//                         which then equals one of the word's four 4-byte
+//                         shifts: each aligned word is compared with the four
+//                         shifts of s1 and of s2 (no byte-aligns, no
+//                         neighbour words until a hit).
+enum : int { kStrMasked = 0, kStrShifted = 1, kStrAligned = 2 };
+
+__host__ __device__ constexpr int str_mode(int n1, int n2) {
+    return (n1 < 4 || n2 < 4) ? kStrMasked : (n1 < 7 || n2 < 7) ? kStrShifted : kStrAligned;
+}
+
 // Returns the 4-bit match mask of the lane's rows (row 64 k + lane -> bit k)
 // for the mini block whose loads str_begin issued; clears ok on corruption.
-// kMasked: some word is shorter than 4 bytes, so 4-byte windows are masked.
-template <bool kMasked>
+template <int kMode>
 __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvalid, StrTile& S,
                                                const StrLds& L, bool& ok) {
     if (!S.ok) { ok = false; return 0; }
@@ -562,58 +590,114 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     if ((uint64_t)total != S.h1 - S.h0) { ok = false; return 0; }
 
     const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
-    const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;  // first 4 bytes
+    // The first 4 bytes of each word (masked for kStrMasked), and for
+    // kStrAligned its shifts: bytes [j, j + 4), j = 1..3.
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
+    uint32_t a1[4], a2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a1[j] = (uint32_t)(P1.p8 >> (8 * j));
+        a2[j] = (uint32_t)(P2.p8 >> (8 * j));
+    }
     cptr<uint8_t> hs = ro(c.heap + S.h0);
     const uint32_t total_b = (uint32_t)(S.h1 - S.h0);
     int nrec = 0;
-    // Hot loop over one segment.  A word whose 4-byte windows match a prefix
-    // is queued with its two successors in LDS (a rare, wave-uniform branch).
+    // Prefix hits of one word x (x1: the word after it): ha -- a start in the
+    // 4 bytes before x (kStrAligned: x equals shift 1..3 of a word); hb -- a
+    // start in x (kStrAligned: at its first byte; otherwise at any of its 4
+    // bytes, from x and its three byte-aligns).
+    auto word_hits = [&](uint32_t x, uint32_t x1, bool& ha, bool& hb) {
+        if (kMode == kStrAligned) {
+            ha = (x == a1[1]) | (x == a1[2]) | (x == a1[3]) | (x == a2[1]) | (x == a2[2]) | (x == a2[3]);
+            hb = (x == a1[0]) | (x == a2[0]);
+            return;
+        }
+        const uint32_t w1 = __builtin_amdgcn_alignbit(x1, x, 8);
+        const uint32_t w2 = __builtin_amdgcn_alignbit(x1, x, 16);
+        const uint32_t w3 = __builtin_amdgcn_alignbit(x1, x, 24);
+        ha = false;
+        if (kMode == kStrMasked)
+            hb = ((x & k1) == a1[0]) | ((w1 & k1) == a1[0]) | ((w2 & k1) == a1[0]) | ((w3 & k1) == a1[0]) |
+                 ((x & k2) == a2[0]) | ((w1 & k2) == a2[0]) | ((w2 & k2) == a2[0]) | ((w3 & k2) == a2[0]);
+        else
+            hb = (x == a1[0]) | (w1 == a1[0]) | (w2 == a1[0]) | (w3 == a1[0]) | (x == a2[0]) | (w1 == a2[0]) |
+                 (w2 == a2[0]) | (w3 == a2[0]);
+    };
+    // Queues the record {q, x, y, z} of the lanes where cnd holds (a record
+    // stands for the 4 starts q .. q + 3, with x, y, z the 12 bytes from q).
+    auto push = [&](bool cnd, uint32_t q, uint32_t x, uint32_t y, uint32_t z) {
+        const uint64_t hb = __builtin_amdgcn_ballot_w64(cnd);
+        if (hb) {
+            const int nh = (int)__popcll(hb);
+            if (nrec + nh > kRecCap) {
+                drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
+                nrec = 0;
+            }
+            if (cnd) L.recs[nrec + bits_below(hb)] = make_uint4(q, x, y, z);
+            nrec += nh;
+        }
+    };
+    uint32_t tail = 0;  // last word of the previous segment (lane 63's fourth)
+    // Hot loop over one segment.  A word with a prefix hit queues its record
+    // in LDS (a rare, wave-uniform branch); kStrAligned gathers the
+    // neighbouring words only then.
     auto scan = [&](const Seg& G, uint32_t base) {
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
             if (base + (uint32_t)it * kWave > nvec) break;  // slots past the mini block hold zeros
             const uint4 w = G.W[it];
-            uint32_t nx, nx2;
-            next_words(G, it, lane, nx, nx2);
-            const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
             const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
+            uint32_t nx = 0, nx2 = 0;
+            if (kMode != kStrAligned) next_words(G, it, lane, nx, nx2);
+            const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
-                const uint32_t w0 = e[wd];
-                const uint32_t w1 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 8);
-                const uint32_t w2 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 16);
-                const uint32_t w3 = __builtin_amdgcn_alignbit(e[wd + 1], e[wd], 24);
-                bool hit;
-                if (kMasked)
-                    hit = ((w0 & k1) == q1) | ((w1 & k1) == q1) | ((w2 & k1) == q1) | ((w3 & k1) == q1) |
-                          ((w0 & k2) == q2) | ((w1 & k2) == q2) | ((w2 & k2) == q2) | ((w3 & k2) == q2);
-                else
-                    hit = (w0 == q1) | (w1 == q1) | (w2 == q1) | (w3 == q1) | (w0 == q2) | (w1 == q2) |
-                          (w2 == q2) | (w3 == q2);
-                const uint64_t hb = __ballot(hit);
-                if (hb) {
-                    const int nh = (int)__popcll(hb);
-                    if (nrec + nh > kRecCap) {
-                        drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
-                        nrec = 0;
-                    }
-                    if (hit) L.recs[nrec + bits_below(hb)] = make_uint4(q0 + 4 * wd, e[wd], e[wd + 1], e[wd + 2]);
-                    nrec += nh;
+                bool ha, hb;
+                word_hits(e[wd], e[wd + 1], ha, hb);
+                if (!__builtin_amdgcn_ballot_w64(ha | hb)) continue;
+                const uint32_t q = q0 + 4u * (uint32_t)wd;
+                if (kMode != kStrAligned) {
+                    push(hb, q, e[wd], e[wd + 1], e[wd + 2]);
+                    continue;
                 }
+                // The word before: the previous lane's last (lane 0: the
+                // previous slot's lane 63, or the segment before's).
+                uint32_t xp;
+                if (wd) {
+                    xp = e[wd - 1];
+                } else {
+                    const uint32_t prev = it ? __builtin_amdgcn_readlane(G.W[it ? it - 1 : 0].w, 63) : tail;
+                    xp = (uint32_t)__builtin_amdgcn_update_dpp((int)prev, (int)w.w, kDppWaveShr1, 0xf, 0xf, false);
+                }
+                uint32_t y1 = e[wd + 1], y2 = e[wd + 2];
+                if (wd >= 2) {
+                    uint32_t a, b;
+                    next_words(G, it, lane, a, b);
+                    y2 = a;
+                    if (wd == 3) { y1 = a; y2 = b; }
+                }
+                push(ha, q - 4u, xp, e[wd], y1);
+                push(hb, q, e[wd], y1, y2);
             }
         }
+        if (kMode == kStrAligned) tail = __builtin_amdgcn_readlane(G.W[kSegIters - 1].w, 63);
     };
     // Two segment buffers in turn: the next segment's loads are in flight
-    // while the current one is compared.
+    // while the current one is compared.  seg_ready makes the wait for the
+    // current buffer explicit before the next loads are issued: left to the
+    // compiler, the join after a conditional load merges the two paths'
+    // outstanding-load counts, and the wait before the compares would then
+    // also cover the loads just issued.
     constexpr uint32_t kSeg = kSegIters * kWave;
     Seg other;
     for (uint32_t base = 0;; base += 2 * kSeg) {
         const bool more1 = base + kSeg < nvec;
+        seg_ready(S.cur);
         if (more1) load_segment(other, S, base + kSeg, nvec, lane);
         scan(S.cur, base);
         if (!more1) break;
         const bool more2 = base + 2 * kSeg < nvec;
+        seg_ready(other);
         if (more2) load_segment(S.cur, S, base + 2 * kSeg, nvec, lane);
         scan(other, base + kSeg);
         if (!more2) break;
@@ -631,12 +715,12 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     return res;
 }
 
-template <bool kMasked>
+template <int kMode>
 __device__ __forceinline__ uint32_t str_pred(CC& c, CP& p, int m, int lane, int nvalid, const StrLds& L,
                                              bool& ok) {
     StrTile S;
     str_begin(c, m, lane, S);
-    return str_finish<kMasked>(c, p, lane, nvalid, S, L, ok);
+    return str_finish<kMode>(c, p, lane, nvalid, S, L, ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -920,10 +1004,14 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
             if (!kStr) {
                 ok_hdr = false;  // unreachable: the launch picks the string instantiation
                 return 0;
-            } else if (P.n1 >= 4 && P.n2 >= 4) {
-                mask &= str_pred<false>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
             } else {
-                mask &= str_pred<true>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+                const int mode = str_mode(P.n1, P.n2);
+                if (mode == kStrAligned)
+                    mask &= str_pred<kStrAligned>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+                else if (mode == kStrShifted)
+                    mask &= str_pred<kStrShifted>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
+                else
+                    mask &= str_pred<kStrMasked>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
             }
         } else {
             const int z = zone_test(Q.cols[P.col], P, m);
@@ -938,8 +1026,13 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
         if (__ballot(mask != 0) == 0) return 0;  // no survivor in this mini block
     }
     if (kEager) {
-        if (PL.n1 >= 4 && PL.n2 >= 4) mask &= str_finish<false>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
-        else mask &= str_finish<true>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+        const int mode = str_mode(PL.n1, PL.n2);
+        if (mode == kStrAligned)
+            mask &= str_finish<kStrAligned>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+        else if (mode == kStrShifted)
+            mask &= str_finish<kStrShifted>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+        else
+            mask &= str_finish<kStrMasked>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
     }
     return mask;
 }
@@ -1000,9 +1093,11 @@ __device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, const Wa
     if (m0 < m1) issue_dense(fc, m0, lane, A);
     for (int m = m0; m < m1; m += 2 * NW) {
         const int m2 = m + NW;
+        dense_ready(A);  // as seg_ready: wait for A before B's loads are issued
         if (m2 < m1) issue_dense(fc, m2, lane, B);
         semi_tile(Q, smem_shared, W, m, lane, A, npend, ok_hdr);
         if (m2 >= m1) break;
+        dense_ready(B);
         if (m2 + NW < m1) issue_dense(fc, m2 + NW, lane, A);
         semi_tile(Q, smem_shared, W, m2, lane, B, npend, ok_hdr);
     }

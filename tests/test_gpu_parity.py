@@ -96,6 +96,46 @@ def test_long_strings_fall_back(ctx):
             G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{a}/{b} {mode}")
 
 
+@pytest.mark.parametrize("n1,n2", [(1, 1), (3, 5), (4, 4), (5, 6), (6, 7), (7, 7), (7, 9), (8, 8),
+                                   (9, 12), (12, 7), (16, 3), (32, 8)])
+def test_string_scan_modes(ctx, n1, n2):
+    """Every scan mode of the string test (some word under 4 bytes, under 7,
+    or both at least 7) on a five-letter alphabet, so that prefix hits are
+    dense and queue overflows happen, with rows long enough that a mini
+    block's heap spans several segments; words are planted at every byte
+    alignment, in order, reversed and overlapping."""
+    G.say("string scan modes", n1, n2)
+    from tests.conftest import to_strings
+    rng = np.random.default_rng(700 + 37 * n1 + n2)
+    alpha = np.frombuffer(b"abcd ", np.uint8)
+    s1 = bytes(rng.choice(alpha[:4], n1))
+    s2 = bytes(rng.choice(alpha[:4], n2))
+    n = 6000
+    items = []
+    for i in range(n):
+        s = bytearray(rng.choice(alpha, int(rng.integers(0, 90))).tobytes())
+        r = rng.random()
+        if r < 0.15:
+            a = int(rng.integers(0, len(s) + 1))
+            s[a:a] = s1
+            b = int(rng.integers(a + n1, len(s) + 1))
+            s[b:b] = s2
+        elif r < 0.25:
+            a = int(rng.integers(0, len(s) + 1))
+            s[a:a] = s2 + s1  # wrong order (unless they overlap into a match)
+        elif r < 0.3:
+            s = bytearray((s1 + s2)[: max(0, n1 + n2 - 1)])  # one byte short
+        items.append(bytes(s))
+    t = {"s": to_strings(items), "g": (np.arange(n) % 5).astype(np.int32)}
+    db = G.make_db(ctx, {"t": t}, chunk_rows=2048)
+    spec = {"fact": "t", "filters": [{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": s1, "s2": s2}],
+            "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
+    want = oracle.run(spec, {"t": t})
+    assert sum(r[-1] for r in want) > 0
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{s1}/{s2} {mode}")
+
+
 @pytest.mark.parametrize("variant", ["3a", "3b"])
 def test_star_join_small(ctx, variant):
     G.say("star join small", variant)
