@@ -63,7 +63,26 @@ struct DevPred {
     int32_t n1, n2;     // STR: word lengths
     uint8_t s1[kMaxWord];
     uint8_t s2[kMaxWord];
+    // STR with both words of at least 7 bytes: lookup table of the aligned-
+    // word test.  The eight 4-byte shifts (bytes [j, j + 4), j < 4) of s1
+    // and s2 sit at slot str_slot(x, tab_rot); a free slot i holds a word
+    // whose slot is not i, so a word x is a shift iff tab[str_slot(x)] == x.
+    // tab_rot = 0: no rotation separates the shifts (no table).
+    uint32_t tab_rot;
+    uint32_t tab[32];
 };
+
+// Slot of a 4-byte word in DevPred::tab: bits 2..6 of x ^ rotr(x, r).
+__host__ __device__ inline uint32_t str_slot(uint32_t x, uint32_t r) {
+    return ((x ^ ((x >> r) | (x << ((32u - r) & 31u)))) & 0x7Cu) >> 2;
+}
+
+// Workgroup LDS of the fused kernel: the string-scan table (DevPred::tab of
+// the plan's last atom, static LDS), then, dynamic, control words, the
+// shared area and the per-wave areas.
+constexpr size_t kLdsCtrlBytes = 64;
+constexpr size_t kLdsStrTabBytes = 128;
+constexpr size_t kLdsHeadBytes = kLdsCtrlBytes + kLdsStrTabBytes;  // counted against the CU's LDS
 
 // Open-addressing table: int32 keys (kEmptyKey = free), payload arrays
 // follow the key array in the same allocation.  When the qualifying keys

@@ -376,6 +376,7 @@ __device__ __forceinline__ StrPattern make_pattern(cptr<uint8_t> w, int n) {
 }
 
 struct StrLds {
+    const uint32_t* tab;  // [32] the workgroup's copy of DevPred::tab (kStrTable)
     uint32_t* offs;    // [257] row start offsets within the mini block's heap
     uint32_t* first1;  // [256] leftmost s1 start (0xffffffff: none)
     uint32_t* last2;   // [256] rightmost s2 start + 1 (0: none)
@@ -536,19 +537,19 @@ __device__ __forceinline__ void drain_records(const StrLds& L, int nrec, uint32_
     wave_lds_sync();
 }
 
-// Scan modes of the string test, by the shorter word's length n:
-//   kStrMasked  (n < 4):  4-byte windows at every byte, masked to n bytes;
-//   kStrShifted (n < 7):  4-byte windows at every byte (three byte-aligns a word);
-//   kStrAligned (n >= 7): every occurrence covers a whole 4-byte-aligned word,
-//                         which then equals one of the word's four 4-byte
-//                         shifts: each aligned word is compared with the four
-//                         shifts of s1 and of s2 (no byte-aligns, no
-//                         neighbour words until a hit).
-enum : int { kStrMasked = 0, kStrShifted = 1, kStrAligned = 2 };
+// Scan modes of the string test:
+//   kStrMasked  (a word under 4 bytes): 4-byte windows at every byte, masked;
+//   kStrShifted (words of 4 bytes or more): 4-byte windows at every byte
+//               (a word and its three byte-aligns);
+//   kStrTable   (both words of 7 bytes or more, with a table): every
+//               occurrence covers a whole 4-byte-aligned word, which then
+//               equals one of the word's four 4-byte shifts; each aligned
+//               word is looked up in the 32-slot LDS table of the eight
+//               shifts (DevPred::tab), one read and one compare a word, and
+//               the neighbour words are gathered only on a hit.
+enum : int { kStrMasked = 0, kStrShifted = 1, kStrTable = 2 };
 
-__host__ __device__ constexpr int str_mode(int n1, int n2) {
-    return (n1 < 4 || n2 < 4) ? kStrMasked : (n1 < 7 || n2 < 7) ? kStrShifted : kStrAligned;
-}
+__device__ __forceinline__ int str_mode(int n1, int n2) { return (n1 < 4 || n2 < 4) ? kStrMasked : kStrShifted; }
 
 // Returns the 4-bit match mask of the lane's rows (row 64 k + lane -> bit k)
 // for the mini block whose loads str_begin issued; clears ok on corruption.
@@ -591,7 +592,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
 
     const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
     // The first 4 bytes of each word (masked for kStrMasked), and for
-    // kStrAligned its shifts: bytes [j, j + 4), j = 1..3.
+    // kStrTable its shifts: bytes [j, j + 4), j = 1..3.
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
     uint32_t a1[4], a2[4];
 #pragma unroll
@@ -603,11 +604,11 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     const uint32_t total_b = (uint32_t)(S.h1 - S.h0);
     int nrec = 0;
     // Prefix hits of one word x (x1: the word after it): ha -- a start in the
-    // 4 bytes before x (kStrAligned: x equals shift 1..3 of a word); hb -- a
-    // start in x (kStrAligned: at its first byte; otherwise at any of its 4
+    // 4 bytes before x (kStrTable: x equals shift 1..3 of a word); hb -- a
+    // start in x (kStrTable: at its first byte; otherwise at any of its 4
     // bytes, from x and its three byte-aligns).
     auto word_hits = [&](uint32_t x, uint32_t x1, bool& ha, bool& hb) {
-        if (kMode == kStrAligned) {
+        if (kMode == kStrTable) {
             ha = (x == a1[1]) | (x == a1[2]) | (x == a1[3]) | (x == a2[1]) | (x == a2[2]) | (x == a2[3]);
             hb = (x == a1[0]) | (x == a2[0]);
             return;
@@ -639,8 +640,9 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     };
     uint32_t tail = 0;  // last word of the previous segment (lane 63's fourth)
     // Hot loop over one segment.  A word with a prefix hit queues its record
-    // in LDS (a rare, wave-uniform branch); kStrAligned gathers the
-    // neighbouring words only then.
+    // in LDS (a rare, wave-uniform branch); kStrTable gathers the
+    // neighbouring words and classifies the hit only then.
+    const uint32_t rot = p.tab_rot;
     auto scan = [&](const Seg& G, uint32_t base) {
 #pragma unroll
         for (int it = 0; it < kSegIters; ++it) {
@@ -648,15 +650,29 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
             const uint4 w = G.W[it];
             const uint32_t q0 = (base + (uint32_t)it * kWave + (uint32_t)lane) * 16u;
             uint32_t nx = 0, nx2 = 0;
-            if (kMode != kStrAligned) next_words(G, it, lane, nx, nx2);
+            if (kMode != kStrTable) next_words(G, it, lane, nx, nx2);
             const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
+            uint32_t t[4];
+            if (kMode == kStrTable) {
+                // The four table reads first, so that they wait together.
+#pragma unroll
+                for (int wd = 0; wd < 4; ++wd) {
+                    const uint32_t y = e[wd] ^ __builtin_amdgcn_alignbit(e[wd], e[wd], rot);
+                    t[wd] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(L.tab) + (y & 0x7Cu));
+                }
+            }
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
                 bool ha, hb;
-                word_hits(e[wd], e[wd + 1], ha, hb);
-                if (!__builtin_amdgcn_ballot_w64(ha | hb)) continue;
+                if (kMode == kStrTable) {
+                    if (!__builtin_amdgcn_ballot_w64(t[wd] == e[wd])) continue;
+                    word_hits(e[wd], 0u, ha, hb);
+                } else {
+                    word_hits(e[wd], e[wd + 1], ha, hb);
+                    if (!__builtin_amdgcn_ballot_w64(ha | hb)) continue;
+                }
                 const uint32_t q = q0 + 4u * (uint32_t)wd;
-                if (kMode != kStrAligned) {
+                if (kMode != kStrTable) {
                     push(hb, q, e[wd], e[wd + 1], e[wd + 2]);
                     continue;
                 }
@@ -680,7 +696,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
                 push(hb, q, e[wd], y1, y2);
             }
         }
-        if (kMode == kStrAligned) tail = __builtin_amdgcn_readlane(G.W[kSegIters - 1].w, 63);
+        if (kMode == kStrTable) tail = __builtin_amdgcn_readlane(G.W[kSegIters - 1].w, 63);
     };
     // Two segment buffers in turn: the next segment's loads are in flight
     // while the current one is compared.  seg_ready makes the wait for the
@@ -946,6 +962,7 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv
 // One mini block of one plan, by one wave (stage A), survivors queued
 // ---------------------------------------------------------------------------
 struct WaveArea {
+    const uint32_t* tab;  // [32] the workgroup's string-scan table
     uint32_t* pend;    // [kPendCap] queued surviving row ids
     int64_t* slots;    // [kMaxSlots][kWave] stage-B values
     uint32_t* offs;    // [260] string row offsets
@@ -991,7 +1008,7 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
-    const StrLds L{W.offs, W.first1, W.last2, W.recs};
+    const StrLds L{W.tab, W.offs, W.first1, W.last2, W.recs};
     const int npreds = Q.npreds;
     CP& PL = Q.preds[npreds - 1];
     StrTile S;
@@ -1005,10 +1022,8 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
                 ok_hdr = false;  // unreachable: the launch picks the string instantiation
                 return 0;
             } else {
-                const int mode = str_mode(P.n1, P.n2);
-                if (mode == kStrAligned)
-                    mask &= str_pred<kStrAligned>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
-                else if (mode == kStrShifted)
+                // (the table is loaded for the plan's last atom only)
+                if (str_mode(P.n1, P.n2) == kStrShifted)
                     mask &= str_pred<kStrShifted>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
                 else
                     mask &= str_pred<kStrMasked>(Q.cols[P.col], P, m, lane, nvalid, L, ok_hdr);
@@ -1026,9 +1041,9 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
         if (__ballot(mask != 0) == 0) return 0;  // no survivor in this mini block
     }
     if (kEager) {
-        const int mode = str_mode(PL.n1, PL.n2);
-        if (mode == kStrAligned)
-            mask &= str_finish<kStrAligned>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
+        const int mode = PL.tab_rot ? kStrTable : str_mode(PL.n1, PL.n2);
+        if (mode == kStrTable)
+            mask &= str_finish<kStrTable>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
         else if (mode == kStrShifted)
             mask &= str_finish<kStrShifted>(Q.cols[PL.col], PL, lane, nvalid, S, L, ok_hdr);
         else
@@ -1115,8 +1130,9 @@ __host__ __device__ constexpr size_t wave_area_bytes(bool str_stage, bool pend_s
     return (pend_stage ? kPendCap * 4 : 0) + (str_stage && kStrBytes > kSlotBytes ? kStrBytes : kSlotBytes);
 }
 
-__device__ __forceinline__ WaveArea wave_area(uint8_t* p, bool pend_stage) {
+__device__ __forceinline__ WaveArea wave_area(uint8_t* p, const uint32_t* tab, bool pend_stage) {
     WaveArea W;
+    W.tab = tab;
     W.pend = reinterpret_cast<uint32_t*>(p);
     uint8_t* shared = p + (pend_stage ? kPendCap * 4 : 0);
     W.slots = reinterpret_cast<int64_t*>(shared);
@@ -1144,7 +1160,11 @@ __device__ unsigned long long flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
 }
 
 // Load a plan's LDS-resident dimension tables and clear its LDS group table.
-__device__ void load_lds_state(CQ& Q, uint8_t* smem_shared) {
+__device__ void load_lds_state(CQ& Q, uint8_t* smem_shared, uint32_t* str_tab) {
+    if (Q.npreds > 0 && threadIdx.x < 32) {
+        CP& PL = Q.preds[Q.npreds - 1];
+        if (PL.kind == PK_STR && PL.tab_rot) str_tab[threadIdx.x] = PL.tab[threadIdx.x];
+    }
     for (int j = 0; j < Q.nprobes; ++j) {
         CH& h = Q.probes[j].h;
         if (h.bits_lds_off >= 0) {
@@ -1251,14 +1271,18 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 template <int NW, bool kStr>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr ? 6 : 4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
+    // Static LDS: its address is known when the kernel is compiled, so the
+    // string scan's table reads take it as an immediate offset.
+    __shared__ __align__(16) uint32_t str_tab[kLdsStrTabBytes / 4];
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
-    uint8_t* shared_area = smem + 64;
+    uint8_t* shared_area = smem + kLdsCtrlBytes;
     const bool str_stage = a.str_stage != 0;
     const int lane = lane_id();
     const int wave = uniform_i32(threadIdx.x >> 6);  // uniform: mini-block headers become scalar loads
     const bool pend_stage = a.pend_stage != 0;
     const WaveArea W =
-        wave_area(smem + 64 + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage, pend_stage), pend_stage);
+        wave_area(shared_area + a.lds_shared + (size_t)wave * wave_area_bytes(str_stage, pend_stage), str_tab,
+                  pend_stage);
     const int total_items = a.item_start[a.nq];
 
     const int home = (int)(blockIdx.x % kXcds);
@@ -1286,7 +1310,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
                 ok_hdr = true;
             }
             __syncthreads();
-            load_lds_state(Q, shared_area);
+            load_lds_state(Q, shared_area, str_tab);
             __syncthreads();
             cur = qi;
             direct |= Q.agg_lds == 0;
@@ -1667,7 +1691,7 @@ hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipSt
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW, kStr>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)kLdsStrTabBytes);
         attr_set = true;
     }
     hipLaunchKernelGGL((fused_kernel<NW, kStr>), dim3(grid), dim3(NW * kWave), lds_bytes, s, a);

@@ -443,6 +443,46 @@ bool pred_range(const dpf_pred& p, int64_t* lo, int64_t* hi) {
     }
 }
 
+// The aligned-word lookup table of a string atom whose words both have at
+// least 7 bytes (every occurrence then covers a whole 4-byte-aligned heap
+// word, equal to one of the word's four 4-byte shifts): the first rotation
+// that gives the distinct shifts distinct slots.  Leaves tab_rot = 0 when
+// none does (the kernels then compare byte windows).
+void build_str_table(DevPred& d) {
+    d.tab_rot = 0;
+    if (d.n1 < 7 || d.n2 < 7) return;
+    uint32_t keys[8];
+    for (int j = 0; j < 4; ++j) {
+        uint32_t a = 0, b = 0;
+        for (int t = 3; t >= 0; --t) {
+            a = (a << 8) | d.s1[j + t];
+            b = (b << 8) | d.s2[j + t];
+        }
+        keys[j] = a;
+        keys[4 + j] = b;
+    }
+    for (uint32_t r = 1; r < 32; ++r) {
+        bool used[32] = {};
+        uint32_t owner[32] = {};
+        bool ok = true;
+        for (uint32_t k : keys) {
+            const uint32_t sl = str_slot(k, r);
+            if (used[sl] && owner[sl] != k) { ok = false; break; }
+            used[sl] = true;
+            owner[sl] = k;
+        }
+        if (!ok) continue;
+        for (uint32_t i = 0; i < 32; ++i) {
+            if (used[i]) { d.tab[i] = owner[i]; continue; }
+            uint32_t e = 0;
+            while (str_slot(e, r) == i) ++e;
+            d.tab[i] = e;
+        }
+        d.tab_rot = r;
+        return;
+    }
+}
+
 // Translates p on column c into d.  *drop = the atom is always true.
 dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<int64_t>& in_vals, DevPred& d,
                           bool* drop) {
@@ -459,6 +499,7 @@ dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<in
         d.n2 = p.n2;
         std::memcpy(d.s1, p.s1, p.n1);
         std::memcpy(d.s2, p.s2, p.n2);
+        build_str_table(d);
         return DPF_OK;
     }
     if (c.enc == DPF_ENC_VARLEN) return fail(DPF_ERR_UNSUPPORTED, "integer predicate on a string column");
@@ -1164,7 +1205,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         a.lds_shared = (int32_t)align_up((size_t)shared, 16);
         a.str_stage = str;
         a.pend_stage = pend;
-        auto lds_for = [&](int w) { return 64 + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
+        auto lds_for = [&](int w) { return kLdsHeadBytes + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
         // Waves per workgroup: large LDS-resident dimension tables are shared
         // by more waves (one copy per workgroup); otherwise small workgroups.
         int waves = o.waves_per_wg;
@@ -1202,7 +1243,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         a.item_start[n] = (int32_t)items;
         // no more workgroups than items: an idle workgroup still claims and signs off
         grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, items));
-        HIP_TRY(launch_fused(a, waves, grid, lds, s));
+        HIP_TRY(launch_fused(a, waves, grid, lds - kLdsStrTabBytes, s));  // the table is static LDS
         ctx->launches++;
     } else {
         return fail(DPF_ERR_INVALID_ARG, "unknown execution mode");
