@@ -779,8 +779,7 @@ constexpr int32_t kDefaultLdsHash = 72 * 1024;
 constexpr int64_t kAggLdsMax = 16 * 1024;
 
 constexpr int64_t kDefaultMbPerItem = 64;  // 16,384 rows
-constexpr int kTargetWavesPerCU = 32;       // string stage: 6 waves per SIMD resident, the rest queued
-                                            // (measured fastest: smaller items, no idle tail)
+constexpr int kTargetWavesPerCU = 24;       // string stage: 6 waves per SIMD (its register occupancy)
 constexpr int kTargetWavesPerCUNoStr = 28;  // without it: 7 waves per SIMD
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
@@ -1210,7 +1209,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         // by more waves (one copy per workgroup); otherwise small workgroups.
         int waves = o.waves_per_wg;
         if (waves == 0) {
-            waves = str ? 8 : 4;  // string batches: measured fastest with 8-wave workgroups
+            waves = 4;
             if (a.lds_shared >= 32 * 1024)
                 for (int w : {16, 8})
                     if ((int64_t)lds_for(w) <= ctx->lds_per_block) { waves = w; break; }
