@@ -1304,6 +1304,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
         CQ& Q = *ro(a.q[qi]);
         if (qi != cur) {
             if (cur >= 0) {
+                // Queued survivors stay valid across the items of one plan:
+                // they go to stage B when the queue fills, at a plan switch
+                // (before the plan's LDS state is replaced) and at the end.
+                // The string instantiation also flushes at every item's end:
+                // its survivors are few, and a full flush in the middle of an
+                // item keeps the workgroup's other waves waiting at the next
+                // item's barrier (measured: without string atoms, deferring
+                // is faster; with them, flushing per item).
+                if (npend) flush_pending(*ro(a.q[cur]), shared_area, W, npend, lane, ok_hdr);
                 __syncthreads();
                 sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
                 if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
@@ -1321,9 +1330,10 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             semi_tiles<NW>(Q, shared_area, W, mb0 + wave, mb1, lane, npend, ok_hdr);
         else
             for (int m = mb0 + wave; m < mb1; m += NW) process_tile<kStr>(Q, shared_area, W, m, lane, npend, ok_hdr);
-        if (npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
+        if (kStr && npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
+        if (npend) flush_pending(*ro(a.q[cur]), shared_area, W, npend, lane, ok_hdr);
         __syncthreads();
         sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
         if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);

@@ -780,7 +780,7 @@ constexpr int64_t kAggLdsMax = 16 * 1024;
 
 constexpr int64_t kDefaultMbPerItem = 64;  // 16,384 rows
 constexpr int kTargetWavesPerCU = 24;       // string stage: 6 waves per SIMD (its register occupancy)
-constexpr int kTargetWavesPerCUNoStr = 28;  // without it: 7 waves per SIMD
+constexpr int kTargetWavesPerCUNoStr = 24;  // without it: also 6 waves per SIMD
 
 // Places the plan's dimension tables and group table in the workgroup's LDS
 // shared area within budget; fills lds offsets and lds_shared.
