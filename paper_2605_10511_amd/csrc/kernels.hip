@@ -941,16 +941,52 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv
         }
     }
     if (!ok) return;
-    // Fact values for slots 0..nloads-1.
+    // Fact values for slots 0..nloads-1, two slots at a time: the group's
+    // loads go out in three rounds (mini-block headers, packed words,
+    // dictionary entries), so that a flush waits for memory three times a
+    // group rather than three times a slot; a DELTA column (a running sum)
+    // decodes on its own.
     const int nloads = Q.nloads;
+    constexpr int kGrp = 2;
+#pragma unroll 1
+    for (int g0 = 0; g0 < nloads; g0 += kGrp) {
+        uint32_t w0[kGrp], w1[kGrp];
+        int64_t base[kGrp];
 #pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {
-        if (s < nloads) {
-            CL& Ld = Q.loads[s];
-            CC& c = Q.cols[Ld.col];
-            int64_t x = decode_at(c, m, i, ok_hdr);
-            if (Ld.dict_val) x = dict_value(c, x, ok_hdr);
-            sv.set(s, x);
+        for (int k = 0; k < kGrp; ++k) {
+            if (g0 + k < nloads) {
+                CC& c = Q.cols[Q.loads[g0 + k].col];
+                w0[k] = ro(c.woff)[m];
+                w1[k] = ro(c.woff)[m + 1];
+                base[k] = ro(c.base)[m];
+            }
+        }
+        uint64_t u[kGrp];
+#pragma unroll
+        for (int k = 0; k < kGrp; ++k) {
+            if (g0 + k < nloads) {
+                CC& c = Q.cols[Q.loads[g0 + k].col];
+                if (c.enc == ENC_DELTA) {
+                    u[k] = (uint64_t)decode_at(c, m, i, ok_hdr);
+                } else {
+                    // the checks of mb_hdr: a corrupt header must not steer a load
+                    const uint32_t nw = w1[k] - w0[k];
+                    const bool hok = (w0[k] <= w1[k]) && (w1[k] <= c.nwords) && ((nw & 7u) == 0) && (nw <= 512u);
+                    ok_hdr = ok_hdr && hok;
+                    const int b = hok ? (int)(nw >> 3) : 0;
+                    u[k] = (uint64_t)base[k] +
+                           (b ? bits_at(ro(c.words) + (hok ? w0[k] : 0u), (uint32_t)i * (uint32_t)b, b) : 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kGrp; ++k) {
+            if (g0 + k < nloads) {
+                CL& Ld = Q.loads[g0 + k];
+                int64_t x = (int64_t)u[k];
+                if (Ld.dict_val) x = dict_value(Q.cols[Ld.col], x, ok_hdr);
+                sv.set(g0 + k, x);
+            }
         }
     }
     int64_t g;
