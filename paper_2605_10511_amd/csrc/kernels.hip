@@ -396,25 +396,28 @@ __device__ __forceinline__ void note_start(const StrLds& L, uint32_t pos, bool m
         atomicMax(&L.last2[r], pos + 1);
 }
 
-// Tests the 4 byte positions of one word (q = its byte offset from the
-// 16-byte-aligned start, e1/e2 = the two words after it) with 8-byte windows.
+// Tests 4 byte positions with 8-byte windows: q is the byte offset of word
+// e0 from the 16-byte-aligned start, e1/e2 the two words after it, and the
+// positions are q + kFirst .. q + kFirst + 3.
+template <int kFirst>
 __device__ __forceinline__ void check_word(const StrLds& L, uint32_t q, uint32_t e0, uint32_t e1, uint32_t e2,
                                            uint32_t s0, uint32_t total, const StrPattern& P1, const StrPattern& P2,
                                            CP& p, cptr<uint8_t> hs) {
     uint32_t k1 = 0, k2 = 0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const uint32_t lo = t ? __builtin_amdgcn_alignbit(e1, e0, 8 * t) : e0;
-        const uint32_t hi = t ? __builtin_amdgcn_alignbit(e2, e1, 8 * t) : e1;
+        const int sh = kFirst + t;  // 0..4
+        const uint32_t lo = sh == 0 ? e0 : sh == 4 ? e1 : __builtin_amdgcn_alignbit(e1, e0, 8 * (sh & 3));
+        const uint32_t hi = sh == 0 ? e1 : sh == 4 ? e2 : __builtin_amdgcn_alignbit(e2, e1, 8 * (sh & 3));
         const uint64_t win8 = (uint64_t)lo | ((uint64_t)hi << 32);
-        const uint32_t qt = q + t;
+        const uint32_t qt = q + (uint32_t)sh;
         const bool inr = qt >= s0 && qt - s0 < total;
         k1 |= (uint32_t)(inr && (win8 & P1.m8) == P1.p8) << t;
         k2 |= (uint32_t)(inr && (win8 & P2.m8) == P2.p8) << t;
     }
     for (uint32_t k = k1 | k2; k; k &= k - 1) {
         const int t = __builtin_ctz(k);
-        note_start(L, q + t - s0, (k1 >> t) & 1u, (k2 >> t) & 1u, p, hs);
+        note_start(L, q + (uint32_t)(kFirst + t) - s0, (k1 >> t) & 1u, (k2 >> t) & 1u, p, hs);
     }
 }
 
@@ -526,13 +529,15 @@ __device__ __forceinline__ void next_words(const Seg& S, int it, int lane, uint3
 
 // Checks queued hit words, one per lane (all lanes at once: a wave pays
 // for the check once per batch of hits, not once per hit).
+// A record {q, e0, e1, e2} stands for the starts q + kFirst .. + 3.
+template <int kFirst>
 __device__ __forceinline__ void drain_records(const StrLds& L, int nrec, uint32_t s0, uint32_t total,
                                               const StrPattern& P1, const StrPattern& P2, CP& p,
                                               cptr<uint8_t> hs, int lane) {
     wave_lds_sync();
     for (int j = lane; j < nrec; j += kWave) {
         const uint4 r = L.recs[j];
-        check_word(L, r.x, r.y, r.z, r.w, s0, total, P1, P2, p, hs);
+        check_word<kFirst>(L, r.x, r.y, r.z, r.w, s0, total, P1, P2, p, hs);
     }
     wave_lds_sync();
 }
@@ -591,47 +596,34 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     if ((uint64_t)total != S.h1 - S.h0) { ok = false; return 0; }
 
     const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
-    // The first 4 bytes of each word (masked for kStrMasked), and for
-    // kStrTable its shifts: bytes [j, j + 4), j = 1..3.
+    // The first 4 bytes of each word (masked for kStrMasked).
     const uint32_t k1 = (uint32_t)P1.m8, k2 = (uint32_t)P2.m8;
-    uint32_t a1[4], a2[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        a1[j] = (uint32_t)(P1.p8 >> (8 * j));
-        a2[j] = (uint32_t)(P2.p8 >> (8 * j));
-    }
+    const uint32_t q1 = (uint32_t)P1.p8, q2 = (uint32_t)P2.p8;
     cptr<uint8_t> hs = ro(c.heap + S.h0);
     const uint32_t total_b = (uint32_t)(S.h1 - S.h0);
     int nrec = 0;
-    // Prefix hits of one word x (x1: the word after it): ha -- a start in the
-    // 4 bytes before x (kStrTable: x equals shift 1..3 of a word); hb -- a
-    // start in x (kStrTable: at its first byte; otherwise at any of its 4
-    // bytes, from x and its three byte-aligns).
-    auto word_hits = [&](uint32_t x, uint32_t x1, bool& ha, bool& hb) {
-        if (kMode == kStrTable) {
-            ha = (x == a1[1]) | (x == a1[2]) | (x == a1[3]) | (x == a2[1]) | (x == a2[2]) | (x == a2[3]);
-            hb = (x == a1[0]) | (x == a2[0]);
-            return;
-        }
+    // Window modes: does a word's 4-byte prefix start in x (x1: the word
+    // after it), at x or one of its three byte-aligns?
+    auto word_hit = [&](uint32_t x, uint32_t x1) -> bool {
         const uint32_t w1 = __builtin_amdgcn_alignbit(x1, x, 8);
         const uint32_t w2 = __builtin_amdgcn_alignbit(x1, x, 16);
         const uint32_t w3 = __builtin_amdgcn_alignbit(x1, x, 24);
-        ha = false;
         if (kMode == kStrMasked)
-            hb = ((x & k1) == a1[0]) | ((w1 & k1) == a1[0]) | ((w2 & k1) == a1[0]) | ((w3 & k1) == a1[0]) |
-                 ((x & k2) == a2[0]) | ((w1 & k2) == a2[0]) | ((w2 & k2) == a2[0]) | ((w3 & k2) == a2[0]);
-        else
-            hb = (x == a1[0]) | (w1 == a1[0]) | (w2 == a1[0]) | (w3 == a1[0]) | (x == a2[0]) | (w1 == a2[0]) |
-                 (w2 == a2[0]) | (w3 == a2[0]);
+            return ((x & k1) == q1) | ((w1 & k1) == q1) | ((w2 & k1) == q1) | ((w3 & k1) == q1) |
+                   ((x & k2) == q2) | ((w1 & k2) == q2) | ((w2 & k2) == q2) | ((w3 & k2) == q2);
+        return (x == q1) | (w1 == q1) | (w2 == q1) | (w3 == q1) | (x == q2) | (w1 == q2) | (w2 == q2) | (w3 == q2);
     };
-    // Queues the record {q, x, y, z} of the lanes where cnd holds (a record
-    // stands for the 4 starts q .. q + 3, with x, y, z the 12 bytes from q).
+    // A record {q, x, y, z} holds the 12 bytes from offset q and stands for
+    // 4 starts: q .. q + 3 in the window modes; q + 1 .. q + 4 for kStrTable,
+    // whose hit on the aligned word y means a start in the 3 bytes before y
+    // or at y itself.
+    constexpr int kFirst = kMode == kStrTable ? 1 : 0;
     auto push = [&](bool cnd, uint32_t q, uint32_t x, uint32_t y, uint32_t z) {
         const uint64_t hb = __builtin_amdgcn_ballot_w64(cnd);
         if (hb) {
             const int nh = (int)__popcll(hb);
             if (nrec + nh > kRecCap) {
-                drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
+                drain_records<kFirst>(L, nrec, s0, total_b, P1, P2, p, hs, lane);
                 nrec = 0;
             }
             if (cnd) L.recs[nrec + bits_below(hb)] = make_uint4(q, x, y, z);
@@ -641,7 +633,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     uint32_t tail = 0;  // last word of the previous segment (lane 63's fourth)
     // Hot loop over one segment.  A word with a prefix hit queues its record
     // in LDS (a rare, wave-uniform branch); kStrTable gathers the
-    // neighbouring words and classifies the hit only then.
+    // neighbouring words only then.
     const uint32_t rot = p.tab_rot;
     auto scan = [&](const Seg& G, uint32_t base) {
 #pragma unroll
@@ -652,48 +644,42 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
             uint32_t nx = 0, nx2 = 0;
             if (kMode != kStrTable) next_words(G, it, lane, nx, nx2);
             const uint32_t e[6] = {w.x, w.y, w.z, w.w, nx, nx2};
-            uint32_t t[4];
-            if (kMode == kStrTable) {
-                // The four table reads first, so that they wait together.
+            if (kMode != kStrTable) {
 #pragma unroll
                 for (int wd = 0; wd < 4; ++wd) {
-                    const uint32_t y = e[wd] ^ __builtin_amdgcn_alignbit(e[wd], e[wd], rot);
-                    t[wd] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(L.tab) + (y & 0x7Cu));
+                    const bool h = word_hit(e[wd], e[wd + 1]);
+                    if (__builtin_amdgcn_ballot_w64(h)) push(h, q0 + 4u * (uint32_t)wd, e[wd], e[wd + 1], e[wd + 2]);
                 }
+                continue;
+            }
+            // kStrTable: the four table reads first, so that they wait together.
+            uint32_t t[4];
+#pragma unroll
+            for (int wd = 0; wd < 4; ++wd) {
+                const uint32_t y = e[wd] ^ __builtin_amdgcn_alignbit(e[wd], e[wd], rot);
+                t[wd] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(L.tab) + (y & 0x7Cu));
             }
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
-                bool ha, hb;
-                if (kMode == kStrTable) {
-                    if (!__builtin_amdgcn_ballot_w64(t[wd] == e[wd])) continue;
-                    word_hits(e[wd], 0u, ha, hb);
-                } else {
-                    word_hits(e[wd], e[wd + 1], ha, hb);
-                    if (!__builtin_amdgcn_ballot_w64(ha | hb)) continue;
-                }
-                const uint32_t q = q0 + 4u * (uint32_t)wd;
-                if (kMode != kStrTable) {
-                    push(hb, q, e[wd], e[wd + 1], e[wd + 2]);
-                    continue;
-                }
+                const bool h = t[wd] == e[wd];
+                if (!__builtin_amdgcn_ballot_w64(h)) continue;
                 // The word before: the previous lane's last (lane 0: the
-                // previous slot's lane 63, or the segment before's).
-                uint32_t xp;
+                // previous slot's lane 63, or the segment before's); the word
+                // after: the next lane's first for the lane's last word.
+                uint32_t xp, y1;
                 if (wd) {
                     xp = e[wd - 1];
                 } else {
                     const uint32_t prev = it ? __builtin_amdgcn_readlane(G.W[it ? it - 1 : 0].w, 63) : tail;
                     xp = (uint32_t)__builtin_amdgcn_update_dpp((int)prev, (int)w.w, kDppWaveShr1, 0xf, 0xf, false);
                 }
-                uint32_t y1 = e[wd + 1], y2 = e[wd + 2];
-                if (wd >= 2) {
-                    uint32_t a, b;
-                    next_words(G, it, lane, a, b);
-                    y2 = a;
-                    if (wd == 3) { y1 = a; y2 = b; }
+                if (wd < 3) {
+                    y1 = e[wd + 1];
+                } else {
+                    uint32_t b;
+                    next_words(G, it, lane, y1, b);
                 }
-                push(ha, q - 4u, xp, e[wd], y1);
-                push(hb, q, e[wd], y1, y2);
+                push(h, q0 + 4u * (uint32_t)wd - 4u, xp, e[wd], y1);
             }
         }
         if (kMode == kStrTable) tail = __builtin_amdgcn_readlane(G.W[kSegIters - 1].w, 63);
@@ -718,7 +704,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
         scan(other, base + kSeg);
         if (!more2) break;
     }
-    if (nrec) drain_records(L, nrec, s0, total_b, P1, P2, p, hs, lane);
+    if (nrec) drain_records<kFirst>(L, nrec, s0, total_b, P1, P2, p, hs, lane);
     wave_lds_sync();
     uint32_t res = 0;
 #pragma unroll

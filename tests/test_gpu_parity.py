@@ -136,6 +136,39 @@ def test_string_scan_modes(ctx, n1, n2):
         G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{s1}/{s2} {mode}")
 
 
+def test_string_table_fallback(ctx):
+    """Words whose first 4-byte shifts are bitwise complements collide in
+    every rotation's slot (x ^ rotr(x, r) is the same for x and ~x), so the
+    plan gets no lookup table and the kernel compares byte windows."""
+    G.say("string table fallback")
+    from tests.conftest import to_strings
+    s1 = b"abcdefg"
+    s2 = bytes(255 - c for c in s1[:4]) + b"xyz"
+    rng = np.random.default_rng(11)
+    alpha = np.frombuffer(b"abcdefgxyz ", np.uint8)
+    n = 5000
+    items = []
+    for i in range(n):
+        s = bytearray(rng.choice(alpha, int(rng.integers(0, 60))).tobytes())
+        r = rng.random()
+        if r < 0.2:
+            a = int(rng.integers(0, len(s) + 1))
+            s[a:a] = s1
+            b = int(rng.integers(a + len(s1), len(s) + 1))
+            s[b:b] = s2
+        elif r < 0.3:
+            s[0:0] = s2 + s1
+        items.append(bytes(s))
+    t = {"s": to_strings(items), "g": (np.arange(n) % 4).astype(np.int32)}
+    db = G.make_db(ctx, {"t": t}, chunk_rows=2048)
+    spec = {"fact": "t", "filters": [{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": s1, "s2": s2}],
+            "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
+    want = oracle.run(spec, {"t": t})
+    assert sum(r[-1] for r in want) > 0
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, mode)
+
+
 @pytest.mark.parametrize("variant", ["3a", "3b"])
 def test_star_join_small(ctx, variant):
     G.say("star join small", variant)
