@@ -1225,11 +1225,11 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         int grid = std::max(1, ctx->ncu * wg);
         if (o.max_workgroups > 0) grid = std::min(grid, o.max_workgroups);
         // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
-        // shrunk for small batches so that every workgroup gets about four
+        // shrunk for small batches so that every workgroup gets about three
         // items, but never below one mini block per wave.
         int64_t mb_per_item = o.rows_per_item / kMB;
         if (mb_per_item == 0) {
-            mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 4LL * grid - 1) / (4LL * grid));
+            mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 3LL * grid - 1) / (3LL * grid));
             mb_per_item = std::max<int64_t>(mb_per_item, waves);
         }
         a.mb_per_item = (int32_t)mb_per_item;
