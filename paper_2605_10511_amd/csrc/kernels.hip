@@ -1712,12 +1712,12 @@ __global__ __launch_bounds__(kBlock) void frag_emit(const DevQuery* __restrict__
 }
 
 __global__ void frag_reset_counts(unsigned long long* c, int n) {
-    if (threadIdx.x < n) c[threadIdx.x] = 0;
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-// Two instantiations per workgroup size: plans with a string atom need the
-// string stage's registers; without it the kernel fits in about half the
-// VGPRs and keeps more waves resident.
+// Two instantiations per workgroup size: only batches with a string atom
+// carry the string stage's code and registers (its segment buffers and
+// record queue); the other instantiation is smaller and spills nothing.
 template <int NW, bool kStr>
 hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
