@@ -285,6 +285,17 @@ dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf_plan* out)
 /* Device memory the plan itself holds (group table, workspace and the hash
  * tables it probes), for admission control. */
 dpf_status dpf_plan_footprint(dpf_plan plan, size_t* hbm_bytes);
+
+/* Chunk pruning (paper Section 3.1.1: predicates checked against zone maps
+ * before the scan).  At plan build, a mini block is excluded when the
+ * min/max its column recorded for the chunk holding it rules out one fact
+ * atom for every row (string columns record lengths: rows shorter than
+ * |s1| + |s2| cannot match), or when one probe's foreign keys all fall
+ * outside the qualifying keys' range.  The fused execution then scans only
+ * the blocks (the smallest chunk of the plan's columns) that keep a mini
+ * block; the fragmented one scans everything, with the same result.
+ * *total_blocks receives the plan's blocks, *scanned_blocks those it scans. */
+dpf_status dpf_plan_blocks(dpf_plan plan, int64_t* scanned_blocks, int64_t* total_blocks);
 void dpf_plan_release(dpf_plan plan);
 
 /* ---------------------------------------------------------------------------

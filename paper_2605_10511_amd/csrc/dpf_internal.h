@@ -154,6 +154,12 @@ struct DevQuery {
     int32_t has_str;
     uint32_t* status;    // device status bits (ST_*)
     int64_t* host_out;   // device address of the pinned output: [status, nrec, records...]
+    // Chunk pruning: null, or the ascending indices of the blocks of
+    // prune_mb mini blocks that the zone maps do not exclude; the fused
+    // kernel's work items then cover those blocks only.
+    const int32_t* live;
+    int32_t nlive;
+    int32_t prune_mb;
 };
 
 struct BatchArgs {

@@ -1346,8 +1346,20 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             cur = qi;
             direct |= Q.agg_lds == 0;
         }
-        const int mb0 = (item - a.item_start[qi]) * a.mb_per_item;
-        const int mb1 = min(mb0 + a.mb_per_item, Q.nmb);
+        // The item's mini blocks: a slice of the plan, or, after chunk
+        // pruning, a slice of one surviving block.
+        const int t = item - a.item_start[qi];
+        int mb0, mb1;
+        if (Q.live) {
+            const int ipc = (Q.prune_mb + a.mb_per_item - 1) / a.mb_per_item;  // items per block
+            const int j = t / ipc;
+            const int blk = ro(Q.live)[j];
+            mb0 = blk * Q.prune_mb + (t - j * ipc) * a.mb_per_item;
+            mb1 = min(min(mb0 + a.mb_per_item, (blk + 1) * Q.prune_mb), Q.nmb);
+        } else {
+            mb0 = t * a.mb_per_item;
+            mb1 = min(mb0 + a.mb_per_item, Q.nmb);
+        }
         if (Q.npreds == 0 && Q.nprobes > 0)
             semi_tiles<NW>(Q, shared_area, W, mb0 + wave, mb1, lane, npend, ok_hdr);
         else

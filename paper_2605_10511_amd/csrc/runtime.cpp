@@ -161,6 +161,7 @@ struct dpf_plan_s {
     size_t host_out_bytes = 0;
     std::vector<KeyOut> keys;
     std::vector<std::pair<int, int>> outcols;  // (acc, kind): kind 0 = acc value
+    int64_t nblocks = 0, nlive = 0;            // chunk pruning: blocks in all, blocks scanned
     int32_t lds_budget = -2;
     int32_t naggs_out = 0;
     bool issued = false;
@@ -851,6 +852,68 @@ void free_frag(dpf_plan p) {
 }
 }  // namespace
 
+// Chunk pruning (paper Section 3.1.1: Kernel #0 checks the predicates
+// against the zone maps and passes on the pages that may qualify).  A mini
+// block is excluded when, by the min/max its column recorded for the chunk
+// holding it at encode time, one fact atom is false for every row, or one
+// probe's foreign keys all miss the qualifying keys' range (the join is
+// inner).  String chunks record lengths: rows shorter than |s1| + |s2|
+// cannot match.  Blocks of prune_mb mini blocks (the smallest chunk of the
+// plan's columns) that hold no surviving mini block are dropped.  Returns
+// prune_mb, with the surviving blocks in live, or 0 when nothing is dropped.
+int32_t prune_blocks(const dpf_plan_desc* desc, int32_t nmb, std::vector<int32_t>& live, int64_t* nblocks) {
+    int64_t unit = INT64_MAX;
+    for (int i = 0; i < desc->ncols; ++i) unit = std::min<int64_t>(unit, desc->cols[i]->host.chunk_rows / kMB);
+    unit = std::max<int64_t>(1, std::min<int64_t>(unit, nmb > 0 ? nmb : 1));
+    *nblocks = nmb > 0 ? (nmb + unit - 1) / unit : 0;
+    if (nmb <= 0) return 0;
+    std::vector<uint8_t> dead((size_t)nmb, 0);
+    bool all_dead = false;
+    auto kill = [&](const HostColumn& c, auto&& excluded) {
+        for (const ChunkInfo& ci : c.chunks) {
+            if (ci.nrows <= 0 || !excluded(ci.min, ci.max)) continue;
+            const int64_t m0 = ci.row_start / kMB;
+            const int64_t m1 = std::min<int64_t>(nmb, (ci.row_start + ci.nrows + kMB - 1) / kMB);
+            if (m0 < m1) std::fill(dead.begin() + m0, dead.begin() + m1, 1);
+        }
+    };
+    for (int i = 0; i < desc->npreds; ++i) {
+        const dpf_pred& pr = desc->preds[i];
+        const HostColumn& c = desc->cols[pr.col]->host;
+        if (pr.op == DPF_OP_STR_CONTAINS_SEQ) {
+            const int64_t need = (int64_t)pr.n1 + pr.n2;
+            kill(c, [&](int64_t, int64_t hi) { return hi < need; });
+        } else if (pr.op == DPF_OP_NE) {
+            kill(c, [&](int64_t lo, int64_t hi) { return lo == hi && lo == pr.a; });
+        } else if (pr.op == DPF_OP_IN) {
+            kill(c, [&](int64_t lo, int64_t hi) {
+                for (int k = 0; k < pr.n_in; ++k)
+                    if (pr.in_values[k] >= lo && pr.in_values[k] <= hi) return false;
+                return true;
+            });
+        } else {
+            int64_t a, b;
+            if (!pred_range(pr, &a, &b)) { all_dead = true; break; }
+            kill(c, [&](int64_t lo, int64_t hi) { return hi < a || lo > b; });
+        }
+    }
+    for (int j = 0; j < desc->nprobes && !all_dead; ++j) {
+        const dpf_hash_stats& hs = desc->probes[j].hash->stats;
+        if (hs.entries == 0) { all_dead = true; break; }
+        kill(desc->cols[desc->probes[j].fk_col]->host,
+             [&](int64_t lo, int64_t hi) { return hi < hs.key_min || lo > hs.key_max; });
+    }
+    live.clear();
+    if (!all_dead)
+        for (int64_t b = 0; b < *nblocks; ++b) {
+            const int64_t m0 = b * unit, m1 = std::min<int64_t>(nmb, m0 + unit);
+            for (int64_t m = m0; m < m1; ++m)
+                if (!dead[(size_t)m]) { live.push_back((int32_t)b); break; }
+        }
+    if ((int64_t)live.size() == *nblocks) { live.clear(); return 0; }
+    return (int32_t)unit;
+}
+
 extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf_plan* out) {
     if (!ctx || !desc || !out) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
     if (ctx->device < 0) return fail(DPF_ERR_INVALID_ARG, "plans need a device context");
@@ -1048,11 +1111,17 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
             if (q.accs[a].t[t].slot >= 0) q.accs[a].t[t].slot = remap[q.accs[a].t[t].slot];
     assign_lds(p, -1);
 
-    // device memory: [DevQuery][agg table][status][counters]
+    // chunk pruning
+    std::vector<int32_t> live;
+    const int32_t prune_mb = prune_blocks(desc, q.nmb, live, &p->nblocks);
+    p->nlive = prune_mb ? (int64_t)live.size() : p->nblocks;
+
+    // device memory: [DevQuery][agg table][status][counters][live blocks]
     const size_t q_off = 0, agg_off = align_up(sizeof(DevQuery), 256);
     const size_t agg_bytes = (size_t)q.ngroups * q.nacc * 8;
     const size_t st_off = align_up(agg_off + agg_bytes, 256), cnt_off = st_off + 256;
-    p->dmem_bytes = cnt_off + (size_t)kCounterWords * 4;
+    const size_t live_off = align_up(cnt_off + (size_t)kCounterWords * 4, 256);
+    p->dmem_bytes = live_off + live.size() * 4;
     p->dmem = ctx->alloc_mem(p->dmem_bytes, DPF_MEM_HBM);
     if (!p->dmem) return bail(fail(DPF_ERR_OOM, "plan workspace"));
     p->host_out_bytes = (2 + (size_t)q.ngroups * (1 + q.nacc)) * 8;
@@ -1067,7 +1136,11 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     q.status = (uint32_t*)(d + st_off);
     p->counters = (uint32_t*)(d + cnt_off);
     q.host_out = host_out_dev;
-    hipError_t e = hipMemset(d + agg_off, 0, p->dmem_bytes - agg_off);
+    q.live = prune_mb ? (const int32_t*)(d + live_off) : nullptr;
+    q.nlive = (int32_t)live.size();
+    q.prune_mb = prune_mb;
+    hipError_t e = hipMemset(d + agg_off, 0, live_off - agg_off);
+    if (e == hipSuccess && !live.empty()) e = hipMemcpy(d + live_off, live.data(), live.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->dq, &q, sizeof q, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
 
@@ -1082,6 +1155,13 @@ extern "C" dpf_status dpf_plan_footprint(dpf_plan plan, size_t* hbm_bytes) {
     size_t b = plan->dmem_bytes;
     for (dpf_hash h : plan->hashes) b += h->bytes;
     *hbm_bytes = b;
+    return DPF_OK;
+}
+
+extern "C" dpf_status dpf_plan_blocks(dpf_plan plan, int64_t* scanned_blocks, int64_t* total_blocks) {
+    if (!plan || !scanned_blocks || !total_blocks) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
+    *scanned_blocks = plan->nlive;
+    *total_blocks = plan->nblocks;
     return DPF_OK;
 }
 
@@ -1199,7 +1279,7 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
             str |= q.has_str != 0;
             pend |= q.npreds > 0 || q.nprobes > 0;
             shared = std::max(shared, q.lds_shared);
-            total_mb += q.nmb;
+            total_mb += q.live ? std::min<int64_t>(q.nmb, (int64_t)q.nlive * q.prune_mb) : q.nmb;
         }
         a.lds_shared = (int32_t)align_up((size_t)shared, 16);
         a.str_stage = str;
@@ -1230,13 +1310,23 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         int64_t mb_per_item = o.rows_per_item / kMB;
         if (mb_per_item == 0) {
             mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 3LL * grid - 1) / (3LL * grid));
+            mb_per_item = std::max<int64_t>(mb_per_item, waves);  // total_mb is 0 when every block is pruned
+            // a pruned plan's items are slices of its blocks: even slices
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->hq.live) {
+                    const int64_t u = plans[i]->hq.prune_mb, k = (u + mb_per_item - 1) / mb_per_item;
+                    mb_per_item = (u + k - 1) / k;
+                    break;
+                }
             mb_per_item = std::max<int64_t>(mb_per_item, waves);
         }
         a.mb_per_item = (int32_t)mb_per_item;
         int64_t items = 0;
         for (int i = 0; i < n; ++i) {
             a.item_start[i] = (int32_t)items;
-            items += (plans[i]->hq.nmb + mb_per_item - 1) / mb_per_item;
+            const DevQuery& q = plans[i]->hq;
+            items += q.live ? (int64_t)q.nlive * ((q.prune_mb + mb_per_item - 1) / mb_per_item)
+                            : (q.nmb + mb_per_item - 1) / mb_per_item;
         }
         if (items > INT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "too many work items; raise rows_per_item");
         a.item_start[n] = (int32_t)items;

@@ -135,6 +135,7 @@ _FUNCS = {
     "dpf_hash_release": (None, [_P]),
     "dpf_plan_build": (C.c_int32, [_P, C.POINTER(dpf_plan_desc), C.POINTER(_P)]),
     "dpf_plan_footprint": (C.c_int32, [_P, C.POINTER(C.c_size_t)]),
+    "dpf_plan_blocks": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dpf_plan_release": (None, [_P]),
     "dpf_execute": (C.c_int32, [_P, C.c_int32, _P, C.POINTER(dpf_exec_opts), _P, C.POINTER(_P)]),
     "dpf_result_get": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -438,6 +439,12 @@ class Plan:
         n = C.c_size_t()
         _check(load().dpf_plan_footprint(self.h, C.byref(n)))
         return n.value
+
+    def blocks(self) -> tuple[int, int]:
+        """(scanned, total) blocks of the fused scan after chunk pruning."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(load().dpf_plan_blocks(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def release(self):
         if self.h:
