@@ -104,7 +104,7 @@ def main():
     # the default warm-up covers them and the timed steps see steady state.
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="wide", choices=["wide", "fa", "sj", "mix", "serve", "prune"])
+    ap.add_argument("--workload", default="wide", choices=["wide", "fa", "sj", "mix", "serve", "prune", "ablation"])
     ap.add_argument("--no-tune", action="store_true", help="mix: skip the knob sweep")
     ap.add_argument("--qps", default="50,100,200,500", help="serve: arrival rates")
     ap.add_argument("--seconds", type=float, default=30.0, help="serve: run time per rate")
@@ -129,6 +129,8 @@ def main():
         return bench_serve(args)
     if args.workload == "prune":
         return bench_prune(args)
+    if args.workload == "ablation":
+        return bench_ablation(args)
 
     import torch
     import oracle
@@ -342,6 +344,66 @@ def bench_prune(args):
         "results_equal": same, "parity_vs_oracle": parity,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_ablation(args):
+    """The gain of fusion and the gain of compression apart (Section 5's
+    breakdown): the wide and star-join queries, fused and fragmented, on
+    compressed columns and on PLAIN ones (every integer at full width;
+    strings stay VARLEN, dimensions keep their encodings)."""
+    import torch
+    from paper_2605_10511_amd import dpf
+
+    ctx = dpf.Context(0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for wl in ("wide", "sj"):
+        tables, encs, spec, nrows, desc, placements = workload(wl, args.scale)
+        fact = spec["fact"]
+        plain = dict(encs)
+        plain[fact] = {c: ("VARLEN" if c == "comment" else "PLAIN") for c in tables[fact]}
+        rows, results = {}, []
+        for form, e in (("compressed", encs), ("plain", plain)):
+            db = dpf.Database(ctx)
+            for name, cols in tables.items():
+                db.add_table(name, cols, e.get(name))
+            plan = db.plan(spec, placements=placements)
+            nbytes = sum(db.tables[fact][c].info().compressed_bytes for c in referenced_columns(spec))
+            for mode, steps, warm in (("FUSED", args.steps, args.warmup), ("FRAGMENTED", max(2, args.frag_steps), 1)):
+                for _ in range(warm):
+                    dpf.execute(ctx, [plan], mode=mode).release()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rs = [dpf.execute(ctx, [plan], mode=mode) for _ in range(steps)]
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                results.append(rs[-1].get(0))
+                for r in rs:
+                    r.release()
+                rows[f"{mode.lower()}_{form}"] = {"ms": ms, "bytes": nbytes}
+                log(f"[ablation] {wl} {mode} {form}: {ms:.3f} ms ({nbytes / 1e9:.3f} GB referenced)")
+            plan.release()
+            for h in plan.hashes:
+                h.release()
+            del db
+        same = all(np.array_equal(results[0], r) for r in results[1:])
+        base = rows["fragmented_plain"]["ms"]
+        out[wl] = {"rows": nrows, "runs": rows, "results_equal": same,
+                   "speedup_fusion_plain": base / rows["fused_plain"]["ms"],
+                   "speedup_compression_fused": rows["fused_plain"]["ms"] / rows["fused_compressed"]["ms"],
+                   "speedup_total": base / rows["fused_compressed"]["ms"]}
+    wide = out["wide"]["runs"]["fused_compressed"]
+    print(json.dumps({
+        "metric": "rows/s and compressed GB/s (% HBM peak), fused vs multi-kernel; p50/p99 query ms",
+        "value": out["wide"]["rows"] / (wide["ms"] * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wide["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "ablation: wide (60M rows) and star join (120M rows), fused / fragmented x "
+                               "compressed / plain columns"},
+        "ablation": out}), flush=True)
 
 
 def bench_mix(args):

@@ -108,7 +108,11 @@ dpf_status dpf_ctx_get_info(dpf_ctx ctx, dpf_ctx_info* out);
  * AUTO picks VARLEN for strings, DELTA for non-decreasing integers, else FOR.
  * ------------------------------------------------------------------------ */
 enum { DPF_TYPE_I32 = 1, DPF_TYPE_I64 = 2, DPF_TYPE_STR = 3 };
-enum { DPF_ENC_AUTO = 0, DPF_ENC_FOR = 1, DPF_ENC_DELTA = 2, DPF_ENC_DICT = 3, DPF_ENC_VARLEN = 4 };
+enum { DPF_ENC_AUTO = 0, DPF_ENC_FOR = 1, DPF_ENC_DELTA = 2, DPF_ENC_DICT = 3, DPF_ENC_VARLEN = 4, DPF_ENC_PLAIN = 5 };
+/* PLAIN (integers only) stores every value at full width, 32 bits for I32
+ * and 64 for I64, in FOR's layout with a fixed base (INT32_MIN / INT64_MIN):
+ * the uncompressed reference that separates the gain of fusion from that of
+ * compression (paper Section 5's breakdown).  AUTO never picks it. */
 enum { DPF_PLACE_HBM = 0, DPF_PLACE_HOST_MAPPED = 1, DPF_PLACE_HOST = 2 };
 
 /* I32/I64: values points to nrows int32_t / int64_t.  STR: str_offsets has

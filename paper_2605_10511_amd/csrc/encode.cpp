@@ -153,6 +153,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
         *err = "VARLEN is for strings";
         return DPF_ERR_INVALID_ARG;
     }
+    if (is_str && enc == DPF_ENC_PLAIN) { *err = "PLAIN is for integers"; return DPF_ERR_INVALID_ARG; }
     auto val = [&](int64_t i) -> int64_t {
         return src.type == DPF_TYPE_I32 ? (int64_t)((const int32_t*)src.values)[i] : ((const int64_t*)src.values)[i];
     };
@@ -161,7 +162,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
         for (int64_t i = 1; i < n && sorted; ++i) sorted = val(i) >= val(i - 1);
         enc = (sorted && n > 0) ? DPF_ENC_DELTA : DPF_ENC_FOR;
     }
-    if (enc < DPF_ENC_FOR || enc > DPF_ENC_VARLEN) { *err = "unknown encoding"; return DPF_ERR_INVALID_ARG; }
+    if (enc < DPF_ENC_FOR || enc > DPF_ENC_PLAIN) { *err = "unknown encoding"; return DPF_ERR_INVALID_ARG; }
 
     HostColumn& c = *out;
     c = HostColumn();
@@ -218,6 +219,16 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
     if (enc == DPF_ENC_DELTA) c.dmin.assign(nmb, 0);
     std::vector<uint8_t> width(nmb, 0);
     const bool delta = enc == DPF_ENC_DELTA;
+    // PLAIN: FOR at full width from a fixed base, whatever the block holds
+    const bool plain = enc == DPF_ENC_PLAIN;
+    const int plain_w = src.type == DPF_TYPE_I32 ? 32 : 64;
+    const int64_t plain_base = src.type == DPF_TYPE_I32 ? (int64_t)INT32_MIN : INT64_MIN;
+    auto prepare = [&](const int64_t* x, int cnt, int64_t* bs, int64_t* dm, uint64_t* u) -> int {
+        if (!plain) return prepare_block(x, cnt, delta, bs, dm, u);
+        *bs = plain_base;
+        for (int i = 0; i < cnt; ++i) u[i] = (uint64_t)x[i] - (uint64_t)plain_base;
+        return cnt ? plain_w : 0;
+    };
     parallel_for(nmb, threads, [&](int64_t a, int64_t b) {
         int64_t x[kMB];
         uint64_t u[kMB];
@@ -225,7 +236,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
             int cnt = (int)std::min<int64_t>(kMB, n - m * kMB);
             for (int i = 0; i < cnt; ++i) x[i] = stream_at(m * kMB + i);
             int64_t dm = 0;
-            width[m] = (uint8_t)prepare_block(x, cnt, delta, &c.base[m], delta ? &dm : nullptr, u);
+            width[m] = (uint8_t)prepare(x, cnt, &c.base[m], delta ? &dm : nullptr, u);
             if (delta) c.dmin[m] = dm;
         }
     });
@@ -249,7 +260,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
             for (int i = 0; i < cnt; ++i) x[i] = stream_at(m * kMB + i);
             for (int i = cnt; i < kMB; ++i) u[i] = 0;
             int64_t bs, dm;
-            int w = prepare_block(x, cnt, delta, &bs, delta ? &dm : nullptr, u);
+            int w = prepare(x, cnt, &bs, delta ? &dm : nullptr, u);
             pack(u, cnt, w, c.words.data() + c.woff[m]);
         }
     });

@@ -280,7 +280,7 @@ DevCol dev_view(const HostColumn& h, const BlobLayout& L, const uint8_t* base) {
     d.heap_bytes = h.heap_bytes;
     d.nwords = (uint32_t)h.nwords;
     d.nmb = (int32_t)h.nmb;
-    d.enc = h.enc;
+    d.enc = h.enc == DPF_ENC_PLAIN ? ENC_FOR : h.enc;  // PLAIN is FOR at full width
     d.ndict = (int32_t)h.dict.size();
     return d;
 }

@@ -162,3 +162,29 @@ def test_generated_tables_roundtrip(hctx):
             assert (off == col.offsets).all() and (data == col.data).all()
         else:
             assert (c.decode() == col).all(), name
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("n", [0, 1, 256, 65536 + 999])
+def test_plain_roundtrip_and_size(hctx, dtype, n):
+    """PLAIN keeps every value at full width (32 or 64 bits) whatever the
+    block holds: size = headers + n * width / 8, rounded up to whole mini
+    blocks; values round-trip bit-exactly, extremes and constants included."""
+    rng = np.random.default_rng(n + (7 if dtype == np.int64 else 0))
+    info = np.iinfo(dtype)
+    x = rng.integers(info.min, info.max, n, dtype=dtype, endpoint=True)
+    if n >= 2:
+        x[0], x[1] = info.min, info.max
+    if n >= 256:
+        x[100:200] = 5  # a constant run does not narrow the width
+    c, y = _roundtrip(hctx, x, "PLAIN")
+    assert y.dtype == dtype and (y == x).all()
+    _check_dir(c, x)
+    nmb = (n + 255) // 256
+    width = 32 if dtype == np.int32 else 64
+    assert c.info().compressed_bytes == nmb * 8 + (nmb + 1) * 4 + nmb * 256 * width // 8
+
+
+def test_plain_rejects_strings(hctx):
+    with pytest.raises(dpf.DpfError):
+        dpf.Column(hctx, to_strings([b"a", b"bc"]), "PLAIN", placement="HOST")

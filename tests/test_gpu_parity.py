@@ -226,6 +226,29 @@ def test_chunk_pruning(ctx):
             G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{name} {mode}")
 
 
+def test_plain_columns(ctx):
+    """Every integer column PLAIN (full width, the uncompressed reference):
+    the wide query with strings and a small star join, fused and fragmented,
+    against the oracle."""
+    G.say("plain columns")
+    t = W.wide_table(120_000, seed=2)
+    w1, w2, _ = W.wide_words(2)
+    enc = {c: ("VARLEN" if c == "comment" else "PLAIN") for c in t}
+    db = G.make_db(ctx, {"fact": t}, {"fact": enc})
+    spec = W.wide_query(w1, w2)
+    want = oracle.run(spec, {"fact": t})
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"wide {mode}")
+    dims = W.sj_dims(seed=3, scale=0.01)
+    fact = W.sj_fact(300_000, seed=3, dims=dims)
+    tables = {"lo": fact, **dims}
+    spec = W.sj_query(part_category=4, date_dow=None)
+    want = oracle.run(spec, tables)
+    db = G.make_db(ctx, tables, {"lo": {c: "PLAIN" for c in fact}})
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"sj {mode}")
+
+
 @pytest.mark.parametrize("variant", ["3a", "3b"])
 def test_star_join_small(ctx, variant):
     G.say("star join small", variant)
