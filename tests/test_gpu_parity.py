@@ -213,8 +213,10 @@ def test_chunk_pruning(ctx):
         ("none", {**base, "filters": [{"col": "date", "op": "GT", "value": 9999}]}, True),
         ("unpruned", {**base, "filters": [{"col": "val", "op": "LT", "value": 500}]}, False),
     ]
+    wants = []
     for name, spec, prunes in cases:
         want = oracle.run(spec, tables)
+        wants.append(want)
         plan = db.plan(spec)
         scanned, total = plan.blocks()
         plan.release()
@@ -224,6 +226,20 @@ def test_chunk_pruning(ctx):
         assert (scanned < total) == prunes, (name, scanned, total)
         for mode in ("FUSED", "FRAGMENTED"):
             G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{name} {mode}")
+    # every case in one fused launch: pruned, unpruned and empty plans share
+    # the work queue, with the default and a caller's item size
+    import torch
+    plans = [db.plan(spec) for _, spec, _ in cases]
+    for kw in ({}, {"rows_per_item": 1024}):
+        res = dpf.execute(ctx, plans, **kw)
+        torch.cuda.synchronize()
+        for k, (name, _, _) in enumerate(cases):
+            G.assert_same(res.get(k), wants[k], f"batch {name} {kw}")
+        res.release()
+    for p in plans:
+        p.release()
+        for h in p.hashes:
+            h.release()
 
 
 def test_plain_columns(ctx):
