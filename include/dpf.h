@@ -309,7 +309,9 @@ enum { DPF_MODE_FUSED = 0, DPF_MODE_FRAGMENTED = 1 };
 typedef struct {
     int32_t mode;
     int32_t wg_per_cu;       /* FUSED: workgroups per compute unit (0 = auto)          */
-    int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = 16384) */
+    int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = auto:   */
+                             /* at most 16384, about three items per workgroup; even   */
+                             /* slices of a pruned plan's blocks)                       */
     int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto)     */
     int32_t waves_per_wg;    /* FUSED: 4, 8 or 16 waves per workgroup (0 = auto)       */
     int32_t max_workgroups;  /* FUSED: cap on the grid (0 = none).  A scan bound by the
