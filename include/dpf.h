@@ -312,7 +312,8 @@ typedef struct {
     int32_t rows_per_item;   /* FUSED: rows per work item, multiple of 256 (0 = auto:   */
                              /* at most 16384, about three items per workgroup; even   */
                              /* slices of a pruned plan's blocks)                       */
-    int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto)     */
+    int32_t lds_hash_bytes;  /* FUSED: LDS budget for dimension tables (-1 = auto:     */
+                             /* 72 KB, none for batches of more than 8 plans)          */
     int32_t waves_per_wg;    /* FUSED: 4, 8 or 16 waves per workgroup (0 = auto)       */
     int32_t max_workgroups;  /* FUSED: cap on the grid (0 = none).  A scan bound by the
                                 host link needs few workgroups; a small grid leaves the

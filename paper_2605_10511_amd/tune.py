@@ -26,7 +26,7 @@ from . import dpf
 
 GRID = {
     "rows_per_item": [16384, 32768, 65536, 131072],
-    "wg_per_cu": [1, 2, 4],
+    "wg_per_cu": [1, 2, 4, 6],
     "lds_hash_bytes": [0, 32768, 65536, 131072],
 }
 MAX_LDS_PER_CU = 160 * 1024
