@@ -109,15 +109,16 @@ struct DevHash {
     int32_t bits_lds_off;  // >= 0: byte offset of an LDS copy of the bitmap
 };
 constexpr int kMaxFilterLog2 = 18;  // 32 KB
-// The filter's two bit positions: top bits of 24-bit products (a full-rate
-// multiply on the GPU, where a 32-bit one issues at quarter rate).  Keys
-// that differ only above bit 23 share their bits: more false positives,
-// never a missed key.
+// The filter's two bit positions, both in one 32-bit word (a blocked
+// filter: one LDS read a probe): top bits of 24-bit products, a full-rate
+// multiply on the GPU where a 32-bit one issues at quarter rate.  Keys that
+// differ only above bit 23 share their bits: more false positives, never a
+// missed key.
 __host__ __device__ inline uint32_t filter_bit(int32_t key, int flog2) {
     return (((uint32_t)key & 0xFFFFFFu) * 0x2545F5u) >> (32 - flog2);
 }
 __host__ __device__ inline uint32_t filter_bit2(int32_t key, int flog2) {
-    return ((((uint32_t)key & 0xFFFFFFu) * 0x9E3779u) + 0x7F4A7C15u) >> (32 - flog2);
+    return (filter_bit(key, flog2) & ~31u) | (((((uint32_t)key & 0xFFFFFFu) * 0x9E3779u) + 0x7F4A7C15u) >> 27);
 }
 
 struct DevProbe {

@@ -779,7 +779,8 @@ __device__ __forceinline__ bool filter_maybe(CH& h, const uint8_t* smem_shared, 
     if (h.filt_lds_off < 0) return true;
     const uint32_t b = filter_bit((int32_t)key, h.flog2), b2 = filter_bit2((int32_t)key, h.flog2);
     const uint32_t* f = reinterpret_cast<const uint32_t*>(smem_shared + h.filt_lds_off);
-    return ((f[b >> 5] >> (b & 31)) & (f[b2 >> 5] >> (b2 & 31)) & 1u) != 0;
+    const uint32_t w = f[b >> 5];  // b2 lies in the same word
+    return ((w >> (b & 31)) & (w >> (b2 & 31)) & 1u) != 0;
 }
 
 // Key-range bitmap test (the table has one: h.bits != nullptr).
