@@ -53,6 +53,8 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.dpf_ctx_create(-1, None, None) == dpf.DPF_ERR_INVALID_ARG
     assert lib.dpf_column_info(None, None) == dpf.DPF_ERR_INVALID_ARG
     assert lib.dpf_execute(None, 1, None, None, None, None) == dpf.DPF_ERR_INVALID_ARG
+    assert lib.dpf_plan_blocks(None, None, None) == dpf.DPF_ERR_INVALID_ARG
+    assert lib.dpf_plan_footprint(None, None) == dpf.DPF_ERR_INVALID_ARG
     assert b"NULL" in lib.dpf_last_error()
 
 
