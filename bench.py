@@ -31,6 +31,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+PCIE_PEAK_GBPS = 63.0  # PCIe Gen5 x16, one direction
 METRIC = "rows/s and compressed GB/s (% HBM peak), fused vs multi-kernel; p50/p99 query ms"
 
 
@@ -71,6 +72,110 @@ def measured_traffic(workload: str):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def host_threads() -> int:
+    """Host threads the CPU baseline uses: the job's CPU share (the thread
+    count the environment sets for OpenMP-style pools, else the CPUs this
+    process may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(spec: dict, tables: dict, nrows: int, what: str) -> tuple:
+    """Times the oracle on one thread and on host_threads() threads over the
+    same tables (the threaded run must return the single-thread records);
+    returns (records, cpu_baseline dict)."""
+    import oracle
+    t0 = time.perf_counter()
+    want = oracle.run(spec, tables)
+    t1 = time.perf_counter()
+    nt = host_threads()
+    want_mt = oracle.run(spec, tables, threads=nt)
+    t2 = time.perf_counter()
+    assert np.array_equal(want, want_mt), "threaded oracle differs from the single-thread oracle"
+    one, many = t1 - t0, t2 - t1
+    log(f"[bench] oracle: 1 thread {one:.2f} s, {nt} threads {many:.2f} s")
+    return want, {"value": nrows / many, "unit": "rows/s", "cores": nt, "kind": "oracle",
+                  "sample": f"{what}: plain C row-at-a-time evaluation over uncompressed columns, rows split "
+                            f"over {nt} threads ({many:.2f} s); single thread {one:.2f} s",
+                  "single_thread_value": nrows / one, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def measure_peaks(ctx, hbm_bytes: int = 4 << 30, host_bytes: int = 1 << 30) -> dict:
+    """Measured ceilings beside the spec peaks: a streaming 16-byte-load
+    kernel over HBM and over pinned host memory (dpf_measure_read), and a
+    pinned host-to-device copy (torch, HIP events); best of several."""
+    import torch
+    from paper_2605_10511_amd import dpf
+    out = {}
+    ms = dpf.measure_read(ctx, "HBM", hbm_bytes, reps=20)
+    out["hbm_read_gbps"] = hbm_bytes / (min(ms[5:]) * 1e-3) / 1e9
+    out["hbm_read_gbps_median"] = hbm_bytes / (float(np.median(ms[5:])) * 1e-3) / 1e9
+    ms = dpf.measure_read(ctx, "HOST_MAPPED", host_bytes, reps=4)
+    out["host_mapped_read_gbps"] = host_bytes / (min(ms[1:]) * 1e-3) / 1e9
+    src = torch.empty(host_bytes, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(host_bytes, dtype=torch.uint8, device="cuda")
+    best = None
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    out["pinned_h2d_gbps"] = host_bytes / (best * 1e-3) / 1e9
+    out["spec_hbm_gbps"] = HBM_PEAK_GBPS
+    out["spec_pcie_gbps"] = PCIE_PEAK_GBPS
+    del src, dst
+    log(f"[bench] measured peaks: HBM read {out['hbm_read_gbps']:.0f} GB/s, host-mapped read "
+        f"{out['host_mapped_read_gbps']:.1f} GB/s, pinned H2D {out['pinned_h2d_gbps']:.1f} GB/s")
+    return out
+
+
+def cold_trials(run, trials: int = 10) -> list:
+    """Device milliseconds of `trials` executions, each after writing a 1 GiB
+    buffer that evicts every XCD's L2 and the Infinity Cache (cold start)."""
+    import torch
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    times = []
+    for k in range(trials):
+        flush.fill_(k & 0xFF)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        r.release()
+    del flush
+    return times
+
+
+def stats(ms: list) -> dict:
+    a = np.asarray(ms, dtype=np.float64)
+    return {"mean_ms": float(a.mean()), "median_ms": float(np.median(a)), "min_ms": float(a.min()),
+            "max_ms": float(a.max()), "n": int(a.size)}
 
 
 def workload(name: str, scale: float):
@@ -117,6 +222,8 @@ def main():
     ap.add_argument("--rows-per-item", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain copy of this many MiB (PMC scale reference)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the bandwidth-ceiling microbenchmarks")
+    ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache trials")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the fused path on a single MI355X "
@@ -158,6 +265,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     kw = dict(wg_per_cu=args.wg_per_cu, rows_per_item=args.rows_per_item)
+    peaks = None if args.no_peaks else measure_peaks(ctx)
     for _ in range(args.warmup):
         dpf.execute(ctx, [plan], **kw).release()
     torch.cuda.synchronize()
@@ -176,7 +284,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launches = (ctx.info().launches - launches0) / args.steps
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    per_launch = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    kern_ms = float(np.mean(per_launch))
     got = results[-1].get(0)
     for r in results:
         r.release()
@@ -206,6 +315,13 @@ def main():
                 "matches_fused": bool(np.array_equal(fgot, got))}
         log(f"[bench] fragmented: {frag['ms_per_step']:.3f} ms/step, {frag['launches_per_query']:.0f} launches")
 
+    cold = None
+    if not args.no_cold:
+        ct = cold_trials(lambda: dpf.execute(ctx, [plan], **kw))
+        cold = dict(stats(ct), gbps_at_mean=alg_bytes / (float(np.mean(ct)) * 1e-3) / 1e9,
+                    protocol="10 trials, each after writing a 1 GiB buffer (evicts L2 and the Infinity Cache)")
+        log(f"[bench] cold: mean {cold['mean_ms']:.3f} ms, median {cold['median_ms']:.3f}, min {cold['min_ms']:.3f}")
+
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.int32, device="cuda")
@@ -217,15 +333,11 @@ def main():
     cpu = None
     parity = None
     if not args.no_oracle:
-        t2 = time.perf_counter()
-        want = oracle.run(spec, tables)
-        ot = time.perf_counter() - t2
+        want, cpu = oracle_baseline(spec, tables, nrows, f"the whole {nrows:,}-row table, one query")
         parity = bool(np.array_equal(want, got))
-        cpu = {"value": nrows / ot, "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole {nrows:,}-row table, one query, single-threaded C row-at-a-time "
-                         f"evaluation over uncompressed columns ({ot:.1f} s)"}
-        log(f"[bench] oracle {ot:.2f} s; GPU result {'==' if parity else '!='} oracle")
+        log(f"[bench] GPU result {'==' if parity else '!='} oracle")
 
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": METRIC,
         "value": rows_s,
@@ -245,9 +357,14 @@ def main():
         "hbm_peak_frac": gbps / HBM_PEAK_GBPS,
         "launches_per_query": launches,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_gbps": (traffic / (kern_ms * 1e-3) / 1e9) if traffic else None,
+                     "frac_of_measured_hbm_read": (achieved / peaks["hbm_read_gbps"]) if peaks else None,
                      "kernel": "fused_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes": alg_bytes},
+        "kernel_ms_per_launch": stats(per_launch),
+        "cold": cold,
+        "measured_peaks": peaks,
         "fragmented": frag,
         "fused_speedup_vs_fragmented": (frag["ms_per_step"] / ms_per_step) if frag else None,
         "cpu_baseline": cpu,
@@ -532,6 +649,27 @@ def bench_mix(args):
     bres.release()
     dms, _, dres = timed(batch_default, args.steps)
     dres.release()
+    # the same batch captured once in a HIP graph and replayed
+    gstream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gstream):
+        with torch.cuda.graph(graph, stream=gstream):
+            gres = dpf.execute(ctx, plans, stream=gstream, **best)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record(gstream)
+    for _ in range(args.steps):
+        graph.replay()
+    g1.record(gstream)
+    torch.cuda.synchronize()
+    gms = g0.elapsed_time(g1) / args.steps
+    graph_eq = all(np.array_equal(gres.get(i), got_b[i]) for i in range(len(plans)))
+    gres.release()
+    del graph
+    log(f"[mix] graph replay {gms:.3f} ms per batch; replayed == eager {graph_eq}")
     sms, swall, sres = timed(solo, max(1, args.steps // 4))
     got_s = [r.get(0) for r in sres]
     fms, fwall, fres = timed(frag, 1)
@@ -585,6 +723,7 @@ def bench_mix(args):
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": "fused_kernel",
                      "kernel_ms": bms},
         "batch_default_knobs_ms": dms,
+        "graph_replay": {"ms": gms, "matches_eager": graph_eq},
         "solo": {"ms": sms, "launches": len(plans), "speedup_of_batch": sms / bms, "knobs": "default"},
         "fragmented": {"ms": fms, "speedup_of_batch": fms / bms, "matches_batch": frag_eq},
         "batch_equals_solo": batch_eq_solo,

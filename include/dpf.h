@@ -348,6 +348,21 @@ dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* 
  * the result's references to its plans, whose memory may be recycled. */
 void dpf_result_release(dpf_result res);
 
+/* ---------------------------------------------------------------------------
+ * Measurement helper (not part of a query; the bandwidth ceilings the scan
+ * is compared against, paper Section 5.1 measures its IO path the same way)
+ * ------------------------------------------------------------------------ */
+/* Read bandwidth that kernels reach from memory of one kind (DPF_MEM_HBM, or
+ * DPF_MEM_HOST_MAPPED: pinned host memory read over the host link).
+ * Allocates bytes (a positive multiple of 16) from the context's allocator,
+ * fills it, then enqueues reps (1..1000) launches of a streaming kernel on
+ * stream -- grid workgroups of 256 lanes (0: 8 per CU), 16-byte loads, four
+ * in flight per lane -- each bracketed by HIP events.  ms[0..reps) receives
+ * each launch's time.  Synchronises the stream and frees the buffer before
+ * returning. */
+dpf_status dpf_measure_read(dpf_ctx ctx, int32_t kind, size_t bytes, int32_t grid, int32_t reps,
+                            dpf_stream stream, float* ms);
+
 #ifdef __cplusplus
 }
 #endif

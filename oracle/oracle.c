@@ -32,6 +32,7 @@
  * with the paper's own numbers is parity unpinned.
  */
 #define _GNU_SOURCE
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -194,7 +195,112 @@ static int64_t ref_value(const orc_ref* r, const orc_column* fact, int64_t row,
     return hit[r->src]->pay[r->idx];
 }
 
-int orc_run(const orc_query* q, int64_t** out_rows, int64_t* out_ngroups, int32_t* out_ncols) {
+/* Rows [r0, r1) of the fact table into the group store g (one row at a
+ * time: the predicate atoms, then every probe, then the key tuple and the
+ * checked products and sums). */
+static int scan_rows(const orc_query* q, const dim_map* dims, int64_t r0, int64_t r1, group_store* g) {
+    int rc = ORC_OK;
+    const dim_entry* hit[ORC_MAX_PROBES];
+    int64_t key[ORC_MAX_KEYS + 1];
+    for (int64_t r = r0; r < r1; ++r) {
+        int ok = 1;
+        for (int32_t i = 0; i < q->npreds && ok; ++i) ok = eval_pred(&q->preds[i], q->fact, r);
+        for (int32_t j = 0; j < q->nprobes && ok; ++j) {
+            hit[j] = probe_dim(&dims[j], q->fact[q->probes[j].fact_fk_col].ival[r]);
+            ok = hit[j] != NULL;
+        }
+        if (!ok) continue;
+        for (int32_t i = 0; i < q->nkeys; ++i) key[i] = ref_value(&q->keys[i], q->fact, r, hit);
+        int64_t* rec = group_find(g, key);
+        if (!rec) { rc = ORC_ERR_OOM; break; }
+        int64_t* acc = rec + q->nkeys;
+        if (__builtin_add_overflow(acc[0], (int64_t)1, &acc[0])) { rc = ORC_ERR_OVERFLOW; break; }
+        int32_t s = 1;
+        for (int32_t a = 0; a < q->naggs && !rc; ++a) {
+            const orc_agg* ag = &q->aggs[a];
+            if (ag->kind == ORC_AGG_COUNT) continue;
+            int64_t prod = 1;
+            for (int32_t t = 0; t < ag->nterms && !rc; ++t) {
+                const orc_term* tm = &ag->terms[t];
+                int64_t v = tm->add;
+                if (tm->has_ref) {
+                    int64_t x = ref_value(&tm->ref, q->fact, r, hit), mx;
+                    if (__builtin_mul_overflow(tm->mul, x, &mx) || __builtin_add_overflow(mx, tm->add, &v))
+                        rc = ORC_ERR_OVERFLOW;
+                }
+                if (!rc && __builtin_mul_overflow(prod, v, &prod)) rc = ORC_ERR_OVERFLOW;
+            }
+            if (!rc && __builtin_add_overflow(acc[s], prod, &acc[s])) rc = ORC_ERR_OVERFLOW;
+            ++s;
+        }
+        if (rc) break;
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Timing-only variant: the rows are cut into nthreads contiguous ranges,    */
+/* each scanned by scan_rows into a group store of its own, and the stores   */
+/* are merged by key with checked adds.  It exists to time the oracle on all */
+/* host cores; the tests check that its records equal the single-thread     */
+/* ones.  (A partial sum that overflows int64 where the whole does not would */
+/* be reported as an overflow here; exact int64 results are unaffected.)    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_query* q;
+    const dim_map* dims;
+    int64_t r0, r1;
+    group_store g;
+    int rc;
+} scan_job;
+
+static void* scan_job_run(void* arg) {
+    scan_job* j = (scan_job*)arg;
+    j->rc = scan_rows(j->q, j->dims, j->r0, j->r1, &j->g);
+    return NULL;
+}
+
+static int merge_store(group_store* into, const group_store* from) {
+    for (int64_t i = 0; i < from->n; ++i) {
+        const int64_t* src = from->rec + i * from->width;
+        int64_t* dst = group_find(into, src);
+        if (!dst) return ORC_ERR_OOM;
+        for (int32_t c = into->nk; c < into->width; ++c)
+            if (__builtin_add_overflow(dst[c], src[c], &dst[c])) return ORC_ERR_OVERFLOW;
+    }
+    return ORC_OK;
+}
+
+static int scan_threaded(const orc_query* q, const dim_map* dims, int64_t nrows, int32_t nthreads,
+                         group_store* g) {
+    if (nthreads > 256) nthreads = 256;
+    scan_job* jobs = (scan_job*)calloc((size_t)nthreads, sizeof(scan_job));
+    pthread_t* tid = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    char* started = (char*)calloc((size_t)nthreads, 1);
+    int rc = (jobs && tid && started) ? ORC_OK : ORC_ERR_OOM;
+    for (int32_t t = 0; t < nthreads && !rc; ++t) {
+        jobs[t].q = q;
+        jobs[t].dims = dims;
+        jobs[t].r0 = nrows * t / nthreads;
+        jobs[t].r1 = nrows * (t + 1) / nthreads;
+        jobs[t].g = *g;  /* empty store of the same shape */
+        if (pthread_create(&tid[t], NULL, scan_job_run, &jobs[t]) == 0) started[t] = 1;
+        else scan_job_run(&jobs[t]);
+    }
+    for (int32_t t = 0; jobs && tid && started && t < nthreads; ++t) {
+        if (started[t]) pthread_join(tid[t], NULL);
+        if (!rc) rc = jobs[t].rc;
+        if (!rc) rc = merge_store(g, &jobs[t].g);
+        free(jobs[t].g.rec);
+    }
+    free(jobs);
+    free(tid);
+    free(started);
+    return rc;
+}
+
+static int run_query(const orc_query* q, int32_t nthreads, int64_t** out_rows, int64_t* out_ngroups,
+                     int32_t* out_ncols) {
     if (!q || !out_rows || !out_ngroups || !out_ncols) return ORC_ERR_INVALID;
     if (q->nfact <= 0 || !q->fact || q->nprobes < 0 || q->nprobes > ORC_MAX_PROBES) return ORC_ERR_INVALID;
     if (q->nkeys < 0 || q->nkeys > ORC_MAX_KEYS || q->naggs < 0 || q->naggs > ORC_MAX_AGGS) return ORC_ERR_INVALID;
@@ -234,41 +340,7 @@ int orc_run(const orc_query* q, int64_t** out_rows, int64_t* out_ngroups, int32_
     }
 
     group_store g = {NULL, 0, 0, q->nkeys, q->nkeys + 1 + nsums};
-    const dim_entry* hit[ORC_MAX_PROBES];
-    int64_t key[ORC_MAX_KEYS + 1];
-    for (int64_t r = 0; r < nrows; ++r) {
-        int ok = 1;
-        for (int32_t i = 0; i < q->npreds && ok; ++i) ok = eval_pred(&q->preds[i], q->fact, r);
-        for (int32_t j = 0; j < q->nprobes && ok; ++j) {
-            hit[j] = probe_dim(&dims[j], q->fact[q->probes[j].fact_fk_col].ival[r]);
-            ok = hit[j] != NULL;
-        }
-        if (!ok) continue;
-        for (int32_t i = 0; i < q->nkeys; ++i) key[i] = ref_value(&q->keys[i], q->fact, r, hit);
-        int64_t* rec = group_find(&g, key);
-        if (!rec) { rc = ORC_ERR_OOM; break; }
-        int64_t* acc = rec + q->nkeys;
-        if (__builtin_add_overflow(acc[0], (int64_t)1, &acc[0])) { rc = ORC_ERR_OVERFLOW; break; }
-        int32_t s = 1;
-        for (int32_t a = 0; a < q->naggs && !rc; ++a) {
-            const orc_agg* ag = &q->aggs[a];
-            if (ag->kind == ORC_AGG_COUNT) continue;
-            int64_t prod = 1;
-            for (int32_t t = 0; t < ag->nterms && !rc; ++t) {
-                const orc_term* tm = &ag->terms[t];
-                int64_t v = tm->add;
-                if (tm->has_ref) {
-                    int64_t x = ref_value(&tm->ref, q->fact, r, hit), mx;
-                    if (__builtin_mul_overflow(tm->mul, x, &mx) || __builtin_add_overflow(mx, tm->add, &v))
-                        rc = ORC_ERR_OVERFLOW;
-                }
-                if (!rc && __builtin_mul_overflow(prod, v, &prod)) rc = ORC_ERR_OVERFLOW;
-            }
-            if (!rc && __builtin_add_overflow(acc[s], prod, &acc[s])) rc = ORC_ERR_OVERFLOW;
-            ++s;
-        }
-        if (rc) break;
-    }
+    rc = nthreads > 1 ? scan_threaded(q, dims, nrows, nthreads, &g) : scan_rows(q, dims, 0, nrows, &g);
 
     if (!rc) {
         int64_t* out = (int64_t*)malloc((size_t)((g.n ? g.n : 1) * ncols_out) * sizeof(int64_t));
@@ -297,6 +369,15 @@ int orc_run(const orc_query* q, int64_t** out_rows, int64_t* out_ngroups, int32_
 done:
     for (int32_t j = 0; j < q->nprobes; ++j) free(dims[j].e);
     return rc;
+}
+
+int orc_run(const orc_query* q, int64_t** out_rows, int64_t* out_ngroups, int32_t* out_ncols) {
+    return run_query(q, 1, out_rows, out_ngroups, out_ncols);
+}
+
+int orc_run_threads(const orc_query* q, int32_t nthreads, int64_t** out_rows, int64_t* out_ngroups,
+                    int32_t* out_ncols) {
+    return run_query(q, nthreads, out_rows, out_ngroups, out_ncols);
 }
 
 void orc_free(int64_t* p) { free(p); }

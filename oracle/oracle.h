@@ -90,6 +90,11 @@ typedef struct {
  * int64 (group keys, then COUNT -> count, SUM -> sum, AVG -> sum, count),
  * ascending by key; free with orc_free.  Returns ORC_OK or an ORC_ERR_*. */
 int orc_run(const orc_query* q, int64_t** out_rows, int64_t* out_ngroups, int32_t* out_ncols);
+/* The same query with the fact rows split over nthreads threads (timing
+ * only: each thread keeps its own groups, merged by key at the end); the
+ * records equal orc_run's. */
+int orc_run_threads(const orc_query* q, int32_t nthreads, int64_t** out_rows, int64_t* out_ngroups,
+                    int32_t* out_ncols);
 void orc_free(int64_t* p);
 int64_t orc_count_filter(const orc_column* cols, int32_t ncols, const orc_pred* preds, int32_t npreds);
 

@@ -169,6 +169,11 @@ struct DevQuery {
 
 struct BatchArgs {
     const DevQuery* q[kMaxBatch];
+    // Per plan: its group table ([ngroups * nacc] int64, zero between
+    // executions) and its status word, in the plan's workspace or in the
+    // library's static scratch area.
+    int64_t* agg[kMaxBatch];
+    uint32_t* status[kMaxBatch];
     int32_t item_start[kMaxBatch + 1];
     int32_t nq;
     int32_t mb_per_item;
@@ -217,15 +222,22 @@ size_t fused_wave_area_bytes(bool str, bool pend);
 hipError_t launch_hash_count(const HashBuildArgs* d_args, int grid, hipStream_t s);
 hipError_t launch_hash_insert(const HashBuildArgs* d_args, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// Bandwidth probe: grid x 256 lanes read bytes (a multiple of 16) at p.
+hipError_t launch_stream_read(const void* p, uint64_t bytes, uint32_t key, uint32_t* sink, int grid,
+                              hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 
-// Fragmented (multi-kernel) execution of one plan.
+// Fragmented (multi-kernel) execution of one plan.  Row lists hold row ids
+// as uint32: plans cover at most 2^32 - 1 rows, and every decoded array is
+// indexed with the id widened to 64 bits.
+typedef uint32_t FragRow;
+static_assert(sizeof(FragRow) == 4 && FragRow(-1) == UINT32_MAX, "row ids must reach 2^32 - 1");
 struct FragBuffers {
     int64_t* dec[kMaxCols];      // decoded integer columns (codes for DICT)
     int64_t* str_off[kMaxCols];  // decoded string offsets [nrows + 1]
     uint8_t* str_bytes[kMaxCols];
     uint8_t* flags;              // [nrows]
-    int32_t* rows[2];            // ping-pong row lists [nrows]
+    FragRow* rows[2];            // ping-pong row lists [nrows]
     int64_t* pay[2][2 * kMaxProbes];  // payload arrays aligned with the row lists
     unsigned long long* counts;  // [kMaxProbes + 2] list lengths
 };

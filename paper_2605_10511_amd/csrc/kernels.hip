@@ -881,22 +881,23 @@ __device__ __forceinline__ int64_t acc_value(CA& A, const S& sv) {
 }
 
 template <class S>
-__device__ __forceinline__ void aggregate_row(CQ& Q, uint8_t* smem_shared, const S& sv,
+__device__ __forceinline__ void aggregate_row(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const S& sv,
                                               int64_t g) {
     const int nacc = Q.nacc;
     unsigned long long* T = Q.agg_lds
         ? reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc
-        : reinterpret_cast<unsigned long long*>(Q.agg) + g * nacc;
+        : gagg + g * nacc;
     atomicAdd(&T[0], 1ull);
     for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
 }
 
 // ---------------------------------------------------------------------------
 // Stage B: probes, value loads and aggregation of one row per lane.  m and i
-// may differ between lanes (rows queued from several mini blocks).
+// may differ between lanes (rows queued from several mini blocks).  gagg is
+// the plan's group table in device memory.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv, int m, int i,
-                                        bool active, bool& ok_hdr) {
+__device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, LdsSlots sv, int m,
+                                        int i, bool active, bool& ok_hdr) {
     bool ok = active;
     const int nprobes = Q.nprobes;
     for (int j = 0; j < nprobes; ++j) {
@@ -978,7 +979,7 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, LdsSlots sv
     }
     int64_t g;
     if (!group_index(Q, sv, g)) { ok_hdr = false; return; }
-    aggregate_row(Q, smem_shared, sv, g);
+    aggregate_row(Q, smem_shared, gagg, sv, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -994,21 +995,21 @@ struct WaveArea {
     uint4* recs;       // [kRecCap] string words with a prefix hit
 };
 
-__device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int& npend, int lane,
-                              bool& ok_hdr) {
+__device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
+                                              int& npend, int lane, bool& ok_hdr) {
     wave_lds_sync();
     for (int base = 0; base < npend; base += kWave) {
         int idx = base + lane;
         bool act = idx < npend;
         uint32_t row = W.pend[act ? idx : 0];
-        stage_b(Q, smem_shared, LdsSlots{W.slots + lane}, (int)(row >> 8), (int)(row & 255u), act, ok_hdr);
+        stage_b(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, (int)(row >> 8), (int)(row & 255u), act, ok_hdr);
     }
     npend = 0;
     wave_lds_sync();
 }
 
-__device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int64_t row0,
-                                                uint32_t mask, int lane, int& npend, bool& ok_hdr) {
+__device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
+                                                int64_t row0, uint32_t mask, int lane, int& npend, bool& ok_hdr) {
     if (__ballot(mask != 0) == 0) return;
     // Queue survivors (wave ballot + mbcnt compaction).
 #pragma unroll
@@ -1018,7 +1019,7 @@ __device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, con
         if (bit) W.pend[npend + bits_below(b)] = (uint32_t)(row0 + 64 * k + lane);
         npend += (int)__popcll(b);
     }
-    if (npend >= kWave) flush_pending(Q, smem_shared, W, npend, lane, ok_hdr);
+    if (npend >= kWave) flush_pending(Q, smem_shared, gagg, W, npend, lane, ok_hdr);
 }
 
 // Stage A of mini block m: returns the mask of rows passing every atom (row
@@ -1076,8 +1077,8 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
 }
 
 template <bool kStr>
-__device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
-                             int& npend, bool& ok_hdr) {
+__device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
+                                             int m, int lane, int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
     const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
     const int npreds = Q.npreds;
@@ -1088,7 +1089,7 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
         for (int k = 0; k < 4; ++k) {
             if (64 * k >= nvalid) break;
             int i = 64 * k + lane;
-            stage_b(Q, smem_shared, LdsSlots{W.slots + lane}, m, i, i < nvalid, ok_hdr);
+            stage_b(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, m, i, i < nvalid, ok_hdr);
         }
         return;
     }
@@ -1096,14 +1097,14 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, const 
     const uint32_t mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
                               ? (kStr ? filter_tile<true, kStr>(Q, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
                               : filter_tile<false, kStr>(Q, W, m, lane, nvalid, ok_hdr);
-    queue_survivors(Q, smem_shared, W, row0, mask, lane, npend, ok_hdr);
+    queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
 // Semi-join stage A of one mini block whose foreign keys issue_dense read:
 // the first (most selective) probe filters; its survivors are probed again,
 // with payloads, in stage B.
-__device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m, int lane,
-                                          const RawDense& R, int& npend, bool& ok_hdr) {
+__device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
+                                          int m, int lane, const RawDense& R, int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
     const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
     uint32_t mask = 0;
@@ -1118,14 +1119,14 @@ __device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, const Wav
         for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
     mask = P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
                              : hash_member4<false>(P0.h, smem_shared, fk, mask);
-    queue_survivors(Q, smem_shared, W, row0, mask, lane, npend, ok_hdr);
+    queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
 // The semi-join tiles m0, m0 + NW, ... < m1 of one wave, two in flight: the
 // next tile's keys are loaded while the current one is probed.
 template <int NW>
-__device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, const WaveArea& W, int m0, int m1,
-                                           int lane, int& npend, bool& ok_hdr) {
+__device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
+                                           int m0, int m1, int lane, int& npend, bool& ok_hdr) {
     CC& fc = Q.cols[Q.probes[0].fk_col];
     RawDense A, B;
     if (m0 < m1) issue_dense(fc, m0, lane, A);
@@ -1133,11 +1134,11 @@ __device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, const Wa
         const int m2 = m + NW;
         dense_ready(A);  // as seg_ready: wait for A before B's loads are issued
         if (m2 < m1) issue_dense(fc, m2, lane, B);
-        semi_tile(Q, smem_shared, W, m, lane, A, npend, ok_hdr);
+        semi_tile(Q, smem_shared, gagg, W, m, lane, A, npend, ok_hdr);
         if (m2 >= m1) break;
         dense_ready(B);
         if (m2 + NW < m1) issue_dense(fc, m2 + NW, lane, A);
-        semi_tile(Q, smem_shared, W, m2, lane, B, npend, ok_hdr);
+        semi_tile(Q, smem_shared, gagg, W, m2, lane, B, npend, ok_hdr);
     }
 }
 
@@ -1169,14 +1170,14 @@ __device__ __forceinline__ WaveArea wave_area(uint8_t* p, const uint32_t* tab, b
 // Merge the workgroup's LDS group table into the plan's global table.  The
 // device-scope adds return their old values, which the caller folds into a
 // sink: once the sink is known the adds have been performed.
-__device__ unsigned long long flush_lds_agg(CQ& Q, uint8_t* smem_shared) {
+__device__ unsigned long long flush_lds_agg(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg) {
     if (!Q.agg_lds) return 0;
     const int64_t n = Q.ngroups * Q.nacc;
     unsigned long long* T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off);
     unsigned long long sink = 0;
     for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
         unsigned long long x = T[e];
-        if (x) sink += atomicAdd(reinterpret_cast<unsigned long long*>(Q.agg) + e, x);
+        if (x) sink += atomicAdd(gagg + e, x);
         T[e] = 0;
     }
     return sink;
@@ -1220,12 +1221,12 @@ __device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p
 
 // Write a plan's non-empty groups as records [group, acc...] into its pinned
 // host buffer (paper Section 3.1: the aggregate is converted into a record
-// format and returned to the host), then clear the device table for the next
-// execution.  Run by one workgroup after every other one has finished.
-__device__ void emit_records(CQ& Q, int32_t* ctrl) {
+// format and returned to the host), then clear the device table T and the
+// status word for the next execution.  Run by one workgroup after every
+// other one has finished.
+__device__ void emit_records(CQ& Q, int32_t* ctrl, unsigned long long* T, uint32_t* status) {
     const int nacc = Q.nacc;
     const int64_t G = Q.ngroups;
-    unsigned long long* T = reinterpret_cast<unsigned long long*>(Q.agg);
     if (threadIdx.x == 0) ctrl[2] = 0;
     __syncthreads();
     for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
@@ -1243,7 +1244,7 @@ __device__ void emit_records(CQ& Q, int32_t* ctrl) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t st = __hip_atomic_exchange(Q.status, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t st = __hip_atomic_exchange(status, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Q.host_out[0] = (int64_t)st;
         Q.host_out[1] = (int64_t)ctrl[2];
     }
@@ -1325,8 +1326,10 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
         while (qi + 1 < a.nq && a.item_start[qi + 1] <= item) ++qi;
         qi = uniform_i32(qi);
         CQ& Q = *ro(a.q[qi]);
+        unsigned long long* const gagg = reinterpret_cast<unsigned long long*>(a.agg[qi]);
         if (qi != cur) {
             if (cur >= 0) {
+                unsigned long long* const cagg = reinterpret_cast<unsigned long long*>(a.agg[cur]);
                 // Queued survivors stay valid across the items of one plan:
                 // they go to stage B when the queue fills, at a plan switch
                 // (before the plan's LDS state is replaced) and at the end.
@@ -1335,10 +1338,10 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
                 // item keeps the workgroup's other waves waiting at the next
                 // item's barrier (measured: without string atoms, deferring
                 // is faster; with them, flushing per item).
-                if (npend) flush_pending(*ro(a.q[cur]), shared_area, W, npend, lane, ok_hdr);
+                if (npend) flush_pending(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
                 __syncthreads();
-                sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
-                if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
+                sink += flush_lds_agg(*ro(a.q[cur]), shared_area, cagg);
+                if (!ok_hdr) sink += atomicOr(a.status[cur], ST_CORRUPT);
                 ok_hdr = true;
             }
             __syncthreads();
@@ -1362,16 +1365,18 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             mb1 = min(mb0 + a.mb_per_item, Q.nmb);
         }
         if (Q.npreds == 0 && Q.nprobes > 0)
-            semi_tiles<NW>(Q, shared_area, W, mb0 + wave, mb1, lane, npend, ok_hdr);
+            semi_tiles<NW>(Q, shared_area, gagg, W, mb0 + wave, mb1, lane, npend, ok_hdr);
         else
-            for (int m = mb0 + wave; m < mb1; m += NW) process_tile<kStr>(Q, shared_area, W, m, lane, npend, ok_hdr);
-        if (kStr && npend) flush_pending(Q, shared_area, W, npend, lane, ok_hdr);
+            for (int m = mb0 + wave; m < mb1; m += NW)
+                process_tile<kStr>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
+        if (kStr && npend) flush_pending(Q, shared_area, gagg, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
-        if (npend) flush_pending(*ro(a.q[cur]), shared_area, W, npend, lane, ok_hdr);
+        unsigned long long* const cagg = reinterpret_cast<unsigned long long*>(a.agg[cur]);
+        if (npend) flush_pending(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
         __syncthreads();
-        sink += flush_lds_agg(*ro(a.q[cur]), shared_area);
-        if (!ok_hdr) sink += atomicOr(ro(a.q[cur])->status, ST_CORRUPT);
+        sink += flush_lds_agg(*ro(a.q[cur]), shared_area, cagg);
+        if (!ok_hdr) sink += atomicOr(a.status[cur], ST_CORRUPT);
     }
     // Last workgroup out emits every plan's records and resets the queue.
     // Publishing: the workgroup's global effects are device-scope atomics,
@@ -1386,7 +1391,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
     __syncthreads();
     if (!ctrl[1]) return;
     __threadfence();
-    for (int qi = 0; qi < a.nq; ++qi) emit_records(*ro(a.q[qi]), ctrl);
+    for (int qi = 0; qi < a.nq; ++qi)
+        emit_records(*ro(a.q[qi]), ctrl, reinterpret_cast<unsigned long long*>(a.agg[qi]), a.status[qi]);
     if (threadIdx.x < 2 * kXcds + 1)  // every other workgroup has left: reset for the next launch
         __hip_atomic_store(ctr(a, threadIdx.x), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence_system();
@@ -1497,6 +1503,28 @@ __global__ __launch_bounds__(kBlock) void hash_insert_kernel(const HashBuildArgs
     if (flags) atomicOr(A.status, flags);
 }
 
+// Bandwidth probe (measurement only, not on the query path): every lane
+// streams 16-byte loads over [p, p + n16 * 16) in a grid-stride loop, four
+// loads in flight, and folds them into one word that is stored only when it
+// equals the caller's value `key`, so that no load can be dropped.
+__global__ __launch_bounds__(256) void stream_read_kernel(const uint4* __restrict__ p, uint64_t n16,
+                                                           uint32_t key, uint32_t* __restrict__ sink) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    cptr<u32x4> v = (cptr<u32x4>)p;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 x0 = v[i], x1 = v[i + stride], x2 = v[i + 2 * stride], x3 = v[i + 3 * stride];
+        acc ^= (x0.x ^ x0.y ^ x0.z ^ x0.w) + (x1.x ^ x1.y ^ x1.z ^ x1.w) + (x2.x ^ x2.y ^ x2.z ^ x2.w) +
+               (x3.x ^ x3.y ^ x3.z ^ x3.w);
+    }
+    for (; i < n16; i += stride) {
+        const u32x4 x = v[i];
+        acc ^= x.x ^ x.y ^ x.z ^ x.w;
+    }
+    if (acc == key) sink[0] = acc;
+}
+
 template <typename T>
 __global__ void fill_kernel(T* p, T v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1593,7 +1621,7 @@ __global__ void frag_filter_str(const DevQuery* __restrict__ q, int pi, const in
 // flags -> row list (order not preserved; aggregation is order-free).  One
 // global atomic per workgroup step of 1024 rows.
 __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restrict__ q, const uint8_t* flags,
-                                                       int32_t* rows, unsigned long long* count) {
+                                                       FragRow* rows, unsigned long long* count) {
     __shared__ uint32_t wcnt[kWaves + 1];
     __shared__ unsigned long long base_s;
     CQ& Q = *ro(q);
@@ -1618,7 +1646,7 @@ __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restric
         __syncthreads();
         unsigned long long o = base_s + wcnt[wave];
         for (int k = 0; k < 4; ++k) {
-            if (f[k]) rows[o + bits_below(bal[k])] = (int32_t)(b0 + wave * 256 + 64 * k + lane);
+            if (f[k]) rows[o + bits_below(bal[k])] = (FragRow)(b0 + wave * 256 + 64 * k + lane);
             o += (uint32_t)__popcll(bal[k]);
         }
         __syncthreads();
@@ -1626,19 +1654,19 @@ __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restric
 }
 
 // all rows -> row list (plans without a fact predicate)
-__global__ void frag_iota(const DevQuery* __restrict__ q, int32_t* rows, unsigned long long* count) {
+__global__ void frag_iota(const DevQuery* __restrict__ q, FragRow* rows, unsigned long long* count) {
     CQ& Q = *ro(q);
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < Q.nrows;
          r += (int64_t)gridDim.x * blockDim.x)
-        rows[r] = (int32_t)r;
+        rows[r] = (FragRow)r;
     if (blockIdx.x == 0 && threadIdx.x == 0) *count = (unsigned long long)Q.nrows;
 }
 
 // Probe j: keep listed rows whose key is found; carry the earlier payload
 // arrays along and append this probe's payloads.
 __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict__ q, int j, const int64_t* fkvals,
-                                                     const int32_t* rin, const unsigned long long* nin,
-                                                     int32_t* rout, unsigned long long* nout,
+                                                     const FragRow* rin, const unsigned long long* nin,
+                                                     FragRow* rout, unsigned long long* nout,
                                                      const FragBuffers fb, int src, int npay_before) {
     CQ& Q = *ro(q);
     CPR& P = Q.probes[j];
@@ -1649,9 +1677,9 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
         int64_t e = b0 + lane;
         bool act = e < n;
         int slot = -1;
-        int32_t r = act ? rin[e] : 0;
+        const FragRow r = act ? rin[e] : 0u;
         if (act) {
-            int64_t fk = fkvals[r];
+            int64_t fk = fkvals[(int64_t)r];
             CC& fc = Q.cols[P.fk_col];
             bool okd = true;
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, okd);
@@ -1675,7 +1703,7 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
 // Aggregate the final row list: fact values gathered from the decoded
 // columns, payloads from the aligned arrays; small group tables are
 // accumulated per workgroup in LDS first.
-__global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restrict__ q, const int32_t* rows,
+__global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restrict__ q, const FragRow* rows,
                                                          const unsigned long long* nrows_list, const FragBuffers fb,
                                                          int src) {
     __shared__ unsigned long long tab[4096];
@@ -1687,7 +1715,7 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
     __syncthreads();
     bool okall = true;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        int32_t r = rows[e];
+        const int64_t r = (int64_t)rows[e];
         RegSlots sv;
         for (int s = 0; s < kMaxSlots; ++s) sv.v[s] = 0;
         int pidx = 0;
@@ -1719,8 +1747,9 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
 
 __global__ __launch_bounds__(kBlock) void frag_emit(const DevQuery* __restrict__ q) {
     __shared__ int32_t ctrl[4];
+    CQ& Q = *ro(q);
     __threadfence();
-    emit_records(*ro(q), ctrl);
+    emit_records(Q, ctrl, reinterpret_cast<unsigned long long*>(Q.agg), Q.status);
     __threadfence_system();
 }
 
@@ -1766,6 +1795,13 @@ hipError_t launch_hash_count(const HashBuildArgs* d_args, int grid, hipStream_t 
 
 hipError_t launch_hash_insert(const HashBuildArgs* d_args, int grid, hipStream_t s) {
     hipLaunchKernelGGL(hash_insert_kernel, dim3(grid), dim3(kBlock), 0, s, d_args);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void* p, uint64_t bytes, uint32_t key, uint32_t* sink, int grid,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<const uint4*>(p),
+                       (uint64_t)(bytes / 16), key, sink);
     return hipGetLastError();
 }
 

@@ -1208,8 +1208,8 @@ dpf_status ensure_frag(dpf_plan p) {
         }
     }
     fb.flags = (uint8_t*)get(n);
-    fb.rows[0] = (int32_t*)get(n * 4);
-    fb.rows[1] = (int32_t*)get(n * 4);
+    fb.rows[0] = (FragRow*)get(n * sizeof(FragRow));
+    fb.rows[1] = (FragRow*)get(n * sizeof(FragRow));
     fb.counts = (unsigned long long*)get(64 * 8);
     if (!fb.flags || !fb.rows[0] || !fb.rows[1] || !fb.counts) goto oom;
     {
@@ -1229,123 +1229,135 @@ oom:
 }
 }  // namespace
 
-extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
-                                  dpf_stream stream, dpf_result* out) {
-    if (!ctx || !plans || !out) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
+namespace {
+// Where a fused launch keeps its scratch state: the work-queue counters and,
+// per plan, the group table and the status word.  clear/clear_bytes: a
+// region to zero (a fill kernel on the stream) before the launch.
+struct FusedWorkspace {
+    uint32_t* counters;
+    int64_t* agg[kMaxBatch];
+    uint32_t* status[kMaxBatch];
+    void* clear;
+    size_t clear_bytes;
+};
+
+dpf_status check_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans) {
     if (ctx->device < 0) return fail(DPF_ERR_INVALID_ARG, "execution needs a device context");
     if (n < 1) return fail(DPF_ERR_INVALID_ARG, "n must be >= 1");
-    dpf_exec_opts o{};
-    o.lds_hash_bytes = -1;
-    if (opts) o = *opts;
     for (int i = 0; i < n; ++i) {
         if (!plans[i] || plans[i]->ctx != ctx) return fail(DPF_ERR_INVALID_ARG, "bad plan handle");
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return fail(DPF_ERR_INVALID_ARG, "a plan appears twice in one execution");
     }
-    hipStream_t s = (hipStream_t)stream;
-    if (o.mode == DPF_MODE_FRAGMENTED) {
-        for (int i = 0; i < n; ++i) {
-            dpf_plan p = plans[i];
-            dpf_status st = ensure_frag(p);
-            if (st != DPF_OK) return st;
-            int launched = run_fragmented(p->dq, p->hq, p->fb, s);
-            if (launched < 0) return fail(DPF_ERR_HIP, "fragmented launch failed");
-            ctx->launches += launched;
+    return DPF_OK;
+}
+
+dpf_status check_fused_opts(int32_t n, const dpf_exec_opts& o) {
+    if (n > kMaxBatch) return fail(DPF_ERR_UNSUPPORTED, "at most 64 plans per fused launch");
+    if (o.rows_per_item && (o.rows_per_item < kMB || o.rows_per_item % kMB))
+        return fail(DPF_ERR_INVALID_ARG, "rows_per_item: multiple of 256");
+    return DPF_OK;
+}
+
+// One launch of the persistent fused kernel over n plans.
+dpf_status launch_fused_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts& o,
+                              const FusedWorkspace& ws, hipStream_t s) {
+    // LDS placement follows the requested budget (re-uploads the
+    // descriptor only when the budget changes).  Auto: none for batches
+    // of more than 8 plans, whose workgroups switch plans often and would
+    // re-copy the tables at every switch (64-query mix: 2.83 -> 2.20 ms).
+    const int32_t auto_lds = n > 8 ? 0 : kDefaultLdsHash;
+    for (int i = 0; i < n; ++i) {
+        dpf_plan p = plans[i];
+        int32_t want = o.lds_hash_bytes < 0 ? auto_lds : o.lds_hash_bytes;
+        if (p->lds_budget != want) {
+            assign_lds(p, want);
+            HIP_TRY(hipMemcpyAsync(p->dq, &p->hq, sizeof(DevQuery), hipMemcpyHostToDevice, s));
         }
-    } else if (o.mode == DPF_MODE_FUSED) {
-        if (n > kMaxBatch) return fail(DPF_ERR_UNSUPPORTED, "at most 64 plans per fused launch");
-        if (o.rows_per_item && (o.rows_per_item < kMB || o.rows_per_item % kMB))
-            return fail(DPF_ERR_INVALID_ARG, "rows_per_item: multiple of 256");
-        // LDS placement follows the requested budget (re-uploads the
-        // descriptor only when the budget changes).  Auto: none for batches
-        // of more than 8 plans, whose workgroups switch plans often and would
-        // re-copy the tables at every switch (64-query mix: 2.83 -> 2.20 ms).
-        const int32_t auto_lds = n > 8 ? 0 : kDefaultLdsHash;
-        for (int i = 0; i < n; ++i) {
-            dpf_plan p = plans[i];
-            int32_t want = o.lds_hash_bytes < 0 ? auto_lds : o.lds_hash_bytes;
-            if (p->lds_budget != want) {
-                assign_lds(p, want);
-                HIP_TRY(hipMemcpyAsync(p->dq, &p->hq, sizeof(DevQuery), hipMemcpyHostToDevice, s));
-            }
-        }
-        BatchArgs a;
-        std::memset(&a, 0, sizeof a);
-        a.nq = n;
-        a.counters = plans[0]->counters;
-        bool str = false, pend = false;
-        int32_t shared = 0;
-        int64_t total_mb = 0;
-        for (int i = 0; i < n; ++i) {
-            const DevQuery& q = plans[i]->hq;
-            a.q[i] = plans[i]->dq;
-            str |= q.has_str != 0;
-            pend |= q.npreds > 0 || q.nprobes > 0;
-            shared = std::max(shared, q.lds_shared);
-            total_mb += q.live ? std::min<int64_t>(q.nmb, (int64_t)q.nlive * q.prune_mb) : q.nmb;
-        }
-        a.lds_shared = (int32_t)align_up((size_t)shared, 16);
-        a.str_stage = str;
-        a.pend_stage = pend;
-        auto lds_for = [&](int w) { return kLdsHeadBytes + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
-        // Waves per workgroup: large LDS-resident dimension tables are shared
-        // by more waves (one copy per workgroup); otherwise small workgroups.
-        int waves = o.waves_per_wg;
-        if (waves == 0) {
-            waves = 4;
-            if (a.lds_shared >= 32 * 1024)
-                for (int w : {16, 8})
-                    if ((int64_t)lds_for(w) <= ctx->lds_per_block) { waves = w; break; }
-        }
-        if (waves != 4 && waves != 8 && waves != 16) return fail(DPF_ERR_INVALID_ARG, "waves_per_wg: 4, 8 or 16");
-        const size_t lds = lds_for(waves);
-        if ((int64_t)lds > ctx->lds_per_block)
-            return fail(DPF_ERR_UNSUPPORTED, "plan LDS needs exceed the workgroup limit; lower lds_hash_bytes");
-        const int lds_cu = 160 * 1024;
-        int wg = o.wg_per_cu;
-        if (wg <= 0) wg = std::max(1, (str ? kTargetWavesPerCU : kTargetWavesPerCUNoStr) / waves);
-        wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
-        int grid = std::max(1, ctx->ncu * wg);
-        if (o.max_workgroups > 0) grid = std::min(grid, o.max_workgroups);
-        // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
-        // shrunk for small batches so that every workgroup gets about three
-        // items, but never below one mini block per wave.
-        int64_t mb_per_item = o.rows_per_item / kMB;
-        if (mb_per_item == 0) {
-            mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 3LL * grid - 1) / (3LL * grid));
-            mb_per_item = std::max<int64_t>(mb_per_item, waves);  // total_mb is 0 when every block is pruned
-            // a pruned plan's items are slices of its blocks: even slices
-            for (int i = 0; i < n; ++i)
-                if (plans[i]->hq.live) {
-                    const int64_t u = plans[i]->hq.prune_mb, k = (u + mb_per_item - 1) / mb_per_item;
-                    mb_per_item = (u + k - 1) / k;
-                    break;
-                }
-            mb_per_item = std::max<int64_t>(mb_per_item, waves);
-        }
-        a.mb_per_item = (int32_t)mb_per_item;
-        int64_t items = 0;
-        for (int i = 0; i < n; ++i) {
-            a.item_start[i] = (int32_t)items;
-            const DevQuery& q = plans[i]->hq;
-            items += q.live ? (int64_t)q.nlive * ((q.prune_mb + mb_per_item - 1) / mb_per_item)
-                            : (q.nmb + mb_per_item - 1) / mb_per_item;
-        }
-        if (items > INT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "too many work items; raise rows_per_item");
-        a.item_start[n] = (int32_t)items;
-        // no more workgroups than items: an idle workgroup still claims and signs off
-        grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, items));
-        HIP_TRY(launch_fused(a, waves, grid, lds - kLdsStrTabBytes, s));  // the table is static LDS
-        ctx->launches++;
-    } else {
-        return fail(DPF_ERR_INVALID_ARG, "unknown execution mode");
     }
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.nq = n;
+    a.counters = ws.counters;
+    bool str = false, pend = false;
+    int32_t shared = 0;
+    int64_t total_mb = 0;
+    for (int i = 0; i < n; ++i) {
+        const DevQuery& q = plans[i]->hq;
+        a.q[i] = plans[i]->dq;
+        a.agg[i] = ws.agg[i];
+        a.status[i] = ws.status[i];
+        str |= q.has_str != 0;
+        pend |= q.npreds > 0 || q.nprobes > 0;
+        shared = std::max(shared, q.lds_shared);
+        total_mb += q.live ? std::min<int64_t>(q.nmb, (int64_t)q.nlive * q.prune_mb) : q.nmb;
+    }
+    a.lds_shared = (int32_t)align_up((size_t)shared, 16);
+    a.str_stage = str;
+    a.pend_stage = pend;
+    auto lds_for = [&](int w) { return kLdsHeadBytes + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
+    // Waves per workgroup: large LDS-resident dimension tables are shared
+    // by more waves (one copy per workgroup); otherwise small workgroups.
+    int waves = o.waves_per_wg;
+    if (waves == 0) {
+        waves = 4;
+        if (a.lds_shared >= 32 * 1024)
+            for (int w : {16, 8})
+                if ((int64_t)lds_for(w) <= ctx->lds_per_block) { waves = w; break; }
+    }
+    if (waves != 4 && waves != 8 && waves != 16) return fail(DPF_ERR_INVALID_ARG, "waves_per_wg: 4, 8 or 16");
+    const size_t lds = lds_for(waves);
+    if ((int64_t)lds > ctx->lds_per_block)
+        return fail(DPF_ERR_UNSUPPORTED, "plan LDS needs exceed the workgroup limit; lower lds_hash_bytes");
+    const int lds_cu = 160 * 1024;
+    int wg = o.wg_per_cu;
+    if (wg <= 0) wg = std::max(1, (str ? kTargetWavesPerCU : kTargetWavesPerCUNoStr) / waves);
+    wg = std::max(1, std::min<int>(wg, (int)(lds_cu / lds)));
+    int grid = std::max(1, ctx->ncu * wg);
+    if (o.max_workgroups > 0) grid = std::min(grid, o.max_workgroups);
+    // Work-item size: the caller's, else 64 mini blocks (16,384 rows),
+    // shrunk for small batches so that every workgroup gets about three
+    // items, but never below one mini block per wave.
+    int64_t mb_per_item = o.rows_per_item / kMB;
+    if (mb_per_item == 0) {
+        mb_per_item = std::min<int64_t>(kDefaultMbPerItem, (total_mb + 3LL * grid - 1) / (3LL * grid));
+        mb_per_item = std::max<int64_t>(mb_per_item, waves);  // total_mb is 0 when every block is pruned
+        // a pruned plan's items are slices of its blocks: even slices
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->hq.live) {
+                const int64_t u = plans[i]->hq.prune_mb, k = (u + mb_per_item - 1) / mb_per_item;
+                mb_per_item = (u + k - 1) / k;
+                break;
+            }
+        mb_per_item = std::max<int64_t>(mb_per_item, waves);
+    }
+    a.mb_per_item = (int32_t)mb_per_item;
+    int64_t items = 0;
+    for (int i = 0; i < n; ++i) {
+        a.item_start[i] = (int32_t)items;
+        const DevQuery& q = plans[i]->hq;
+        items += q.live ? (int64_t)q.nlive * ((q.prune_mb + mb_per_item - 1) / mb_per_item)
+                        : (q.nmb + mb_per_item - 1) / mb_per_item;
+    }
+    if (items > INT32_MAX) return fail(DPF_ERR_UNSUPPORTED, "too many work items; raise rows_per_item");
+    a.item_start[n] = (int32_t)items;
+    // no more workgroups than items: an idle workgroup still claims and signs off
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, items));
+    if (ws.clear_bytes) HIP_TRY(launch_fill_i32((int32_t*)ws.clear, 0, (int64_t)(ws.clear_bytes / 4), s));
+    HIP_TRY(launch_fused(a, waves, grid, lds - kLdsStrTabBytes, s));  // the table is static LDS
+    ctx->launches += ws.clear_bytes ? 2 : 1;
+    return DPF_OK;
+}
+
+// The result handle of an execution; with_event records a completion event
+// (not under stream capture) that dpf_result_release waits for.
+dpf_status make_result(int32_t n, const dpf_plan* plans, hipStream_t s, bool with_event, dpf_result* out) {
     dpf_result r = new (std::nothrow) dpf_result_s();
     if (!r) return fail(DPF_ERR_OOM, "result");
     // Completion event for the release (not under graph capture, where the
     // caller owns the ordering of replays).
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+    if (with_event && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
         if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) r->done = nullptr;
         else if (hipEventRecord(r->done, s) != hipSuccess) {
             (void)hipEventDestroy(r->done);
@@ -1362,6 +1374,44 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
     r->read.assign(n, 0);
     *out = r;
     return DPF_OK;
+}
+}  // namespace
+
+extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
+                                  dpf_stream stream, dpf_result* out) {
+    if (!ctx || !plans || !out) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
+    dpf_status st = check_batch(ctx, n, plans);
+    if (st != DPF_OK) return st;
+    dpf_exec_opts o{};
+    o.lds_hash_bytes = -1;
+    if (opts) o = *opts;
+    hipStream_t s = (hipStream_t)stream;
+    if (o.mode == DPF_MODE_FRAGMENTED) {
+        for (int i = 0; i < n; ++i) {
+            dpf_plan p = plans[i];
+            st = ensure_frag(p);
+            if (st != DPF_OK) return st;
+            int launched = run_fragmented(p->dq, p->hq, p->fb, s);
+            if (launched < 0) return fail(DPF_ERR_HIP, "fragmented launch failed");
+            ctx->launches += launched;
+        }
+    } else if (o.mode == DPF_MODE_FUSED) {
+        st = check_fused_opts(n, o);
+        if (st != DPF_OK) return st;
+        // The plans' own workspaces: the first plan's queue counters, each
+        // plan's group table and status word (zero between executions).
+        FusedWorkspace ws{};
+        ws.counters = plans[0]->counters;
+        for (int i = 0; i < n; ++i) {
+            ws.agg[i] = plans[i]->hq.agg;
+            ws.status[i] = plans[i]->hq.status;
+        }
+        st = launch_fused_batch(ctx, n, plans, o, ws, s);
+        if (st != DPF_OK) return st;
+    } else {
+        return fail(DPF_ERR_INVALID_ARG, "unknown execution mode");
+    }
+    return make_result(n, plans, s, true, out);
 }
 
 extern "C" dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* ncols, const int64_t** rows) {
@@ -1410,6 +1460,56 @@ extern "C" dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups
     *ncols = nout;
     *rows = res->rows[i].data();
     return DPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Measurement helper: read bandwidth from HBM or from pinned host memory
+// ---------------------------------------------------------------------------
+extern "C" dpf_status dpf_measure_read(dpf_ctx ctx, int32_t kind, size_t bytes, int32_t grid, int32_t reps,
+                                       dpf_stream stream, float* ms) {
+    if (!ctx || !ms) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->device < 0) return fail(DPF_ERR_INVALID_ARG, "measurement needs a device context");
+    if (kind != DPF_MEM_HBM && kind != DPF_MEM_HOST_MAPPED) return fail(DPF_ERR_INVALID_ARG, "unknown memory kind");
+    if (bytes < 16 || bytes % 16 || reps < 1 || reps > 1000 || grid < 0)
+        return fail(DPF_ERR_INVALID_ARG, "bytes: a positive multiple of 16; reps: 1..1000; grid >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (grid == 0) grid = ctx->ncu * 8;
+    uint8_t* buf = (uint8_t*)ctx->alloc_mem(bytes, kind);
+    uint32_t* sink = (uint32_t*)ctx->alloc_mem(256, DPF_MEM_HBM);
+    std::vector<hipEvent_t> ev((size_t)reps + 1, nullptr);
+    dpf_status st = DPF_OK;
+    const void* src = buf;
+    if (!buf || !sink) {
+        st = fail(DPF_ERR_OOM, "measurement buffer");
+    } else if (kind == DPF_MEM_HOST_MAPPED) {
+        std::memset(buf, 0x5A, bytes);
+        src = ctx->device_ptr(buf);
+        if (!src) st = fail(DPF_ERR_HIP, "hipHostGetDevicePointer(measurement buffer)");
+    } else {
+        hipError_t e = hipMemsetAsync(buf, 0x5A, bytes, s);
+        if (e != hipSuccess) st = hip_fail(e, "hipMemsetAsync(measurement buffer)");
+    }
+    for (size_t i = 0; st == DPF_OK && i < ev.size(); ++i) {
+        hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) { ev[i] = nullptr; st = hip_fail(e, "hipEventCreate"); }
+    }
+    if (st == DPF_OK) {
+        hipError_t e = hipEventRecord(ev[0], s);
+        for (int32_t r = 0; e == hipSuccess && r < reps; ++r) {
+            e = launch_stream_read(src, bytes, 0x9E3779B9u, sink, grid, s);
+            if (e == hipSuccess) e = hipEventRecord(ev[(size_t)r + 1], s);
+            ctx->launches++;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[(size_t)reps]);
+        for (int32_t r = 0; e == hipSuccess && r < reps; ++r) e = hipEventElapsedTime(&ms[r], ev[(size_t)r], ev[(size_t)r + 1]);
+        if (e != hipSuccess) st = hip_fail(e, "measurement launch");
+    }
+    (void)hipStreamSynchronize(s);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (buf) ctx->free_mem(buf, kind);
+    if (sink) ctx->free_mem(sink, DPF_MEM_HBM);
+    return st;
 }
 
 extern "C" void dpf_result_release(dpf_result res) {

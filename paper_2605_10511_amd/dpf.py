@@ -141,6 +141,7 @@ _FUNCS = {
     "dpf_result_get": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                    C.POINTER(C.POINTER(C.c_int64))]),
     "dpf_result_release": (None, [_P]),
+    "dpf_measure_read": (C.c_int32, [_P, C.c_int32, C.c_size_t, C.c_int32, C.c_int32, _P, C.POINTER(C.c_float)]),
 }
 
 _lib = None

@@ -58,7 +58,7 @@ class _Batch:
 class Server:
     def __init__(self, ctx: dpf.Context, db: dpf.Database, nstreams: int = 4, slots: int = 8,
                  state_budget: int = 4 << 30, placements: dict | None = None, host_tables=(),
-                 host_knobs: dict | None = None):
+                 host_knobs: dict | None = None, max_batch: int = 64):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -73,6 +73,11 @@ class Server:
         self.host_tables = set(host_tables)
         self.host_knobs = dict(host_knobs) if host_knobs is not None else {"max_workgroups": 64}
         self.host_stream = torch.cuda.Stream() if self.host_tables else None  # default priority
+        self.max_batch = max(1, min(64, max_batch))  # plans per fused launch
+        # what the loop did: plans per launched batch, and the most batches
+        # that were on the device at the same time
+        self.batch_sizes: list[int] = []
+        self.max_inflight = 0
 
     # -- preparation -------------------------------------------------------
     def _hash(self, pr: dict) -> dpf.Hash:
@@ -153,7 +158,7 @@ class Server:
             while free and ready and nin < self.slots:
                 batch = []
                 fp = 0
-                while ready and nin + len(batch) < self.slots and len(batch) < 64:
+                while ready and nin + len(batch) < self.slots and len(batch) < self.max_batch:
                     r = ready[0]
                     if used + fp + r.footprint > self.state_budget and (batch or inflight):
                         break  # wait for state to drain
@@ -176,6 +181,8 @@ class Server:
                 inflight.append(b)
                 used += fp
                 nin += len(batch)
+                self.batch_sizes.append(len(batch))
+                self.max_inflight = max(self.max_inflight, len(inflight))
                 progressed = True
             # host-table requests: one at a time on their own stream
             if ready_host and not host_busy:
@@ -191,6 +198,8 @@ class Server:
                 inflight.append(b)
                 used += r.footprint
                 host_busy = True
+                self.batch_sizes.append(1)
+                self.max_inflight = max(self.max_inflight, len(inflight))
                 progressed = True
             if not progressed:
                 nxt = reqs[i].t - (time.perf_counter() - t0) if i < len(reqs) else 0.0

@@ -74,9 +74,10 @@ def test_wide_strings(ctx):
             G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{a}/{b} {mode}")
 
 
-def test_long_strings_fall_back(ctx):
-    """Mini blocks whose strings exceed the LDS staging area take the
-    lane-per-row path."""
+def test_long_strings(ctx):
+    """Strings of up to 300 bytes: a mini block's heap spans up to ~38 of the
+    string scan's 2 KB segments, so both segment buffers alternate many times
+    and hit records carry across segment boundaries."""
     G.say("long strings")
     from tests.conftest import to_strings
     rng = np.random.default_rng(4)

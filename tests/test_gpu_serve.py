@@ -52,9 +52,20 @@ def test_tuner_picks_a_measured_point(env, tmp_path):
         p.release()
 
 
-def test_served_results_equal_oracle_and_alone(env):
+def _alone(ctx, db, srv, r):
     import torch
-    from paper_2605_10511_amd import dpf, serve
+    from paper_2605_10511_amd import dpf
+    p = db.plan(r.spec, hashes=[srv._hash(pr) for pr in r.spec.get("probes", [])])
+    out = dpf.execute(ctx, [p])
+    torch.cuda.synchronize()
+    rows = out.get(0)
+    out.release()
+    p.release()
+    return rows
+
+
+def test_served_results_equal_oracle_and_alone(env):
+    from paper_2605_10511_amd import serve
     ctx, db, tables = env
     gen = W.serve_requests(11, 400.0, 0.1, "res")
     reqs = [serve.Request(t, k, s, "res") for t, k, s in gen]
@@ -65,13 +76,31 @@ def test_served_results_equal_oracle_and_alone(env):
     assert all(r.done >= r.t for r in done)
     for r in done:
         G.assert_same(r.rows, oracle.run(r.spec, tables), f"served {r.template} at {r.t:.4f}")
-    for r in done[:6]:
-        p = db.plan(r.spec, hashes=[srv._hash(pr) for pr in r.spec.get("probes", [])])
-        out = dpf.execute(ctx, [p])
-        torch.cuda.synchronize()
-        G.assert_same(out.get(0), r.rows, "alone vs served")
-        out.release()
-        p.release()
+        G.assert_same(_alone(ctx, db, srv, r), r.rows, "alone vs served")
+    srv.close()
+
+
+def test_burst_mixes_requests(env):
+    """A burst of 40 requests at time 0 with 4 plans per launch: the loop
+    must put several requests into one launch and have several launches on
+    the device at once (continuous batching, not a queue), and every result
+    must equal the oracle's and a lone execution's."""
+    from paper_2605_10511_amd import serve
+    ctx, db, tables = env
+    gen = W.serve_requests(21, 1000.0, 0.06, "res")[:40]
+    reqs = [serve.Request(0.0, k, s, "res") for _, k, s in gen]
+    assert len(reqs) == 40
+    srv = serve.Server(ctx, db, nstreams=4, slots=16, state_budget=1 << 30, max_batch=4)
+    srv.warm(reqs)
+    G.say(f"burst of {len(reqs)} requests")
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert max(srv.batch_sizes) > 1, srv.batch_sizes
+    assert srv.max_inflight > 1, srv.max_inflight
+    G.say(f"batches {srv.batch_sizes}, at most {srv.max_inflight} in flight")
+    for r in done:
+        G.assert_same(r.rows, oracle.run(r.spec, tables), f"burst {r.template}")
+        G.assert_same(_alone(ctx, db, srv, r), r.rows, "alone vs burst")
     srv.close()
 
 

@@ -351,3 +351,34 @@ def test_broken_oracle_fails_a_pin(idx, hand_cases, tmp_path):
     finally:
         oracle.use_library(None)
     assert failed, f"mutant {idx} passed every pin: {new}"
+
+
+# --------------------------------------------------------------------------
+# The timing-only threaded oracle returns the single-thread records
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("threads", [2, 3, 8, 64])
+def test_threaded_oracle_equals_single_thread(threads):
+    t = W.fa_table(400_003, seed=31)
+    for spec in (W.fa_query(), dict(W.fa_query(), filters=[])):
+        assert np.array_equal(oracle.run(spec, {"fact": t}, threads=threads), oracle.run(spec, {"fact": t}))
+    wide = W.wide_table(60_000, seed=2)
+    w1, w2, _ = W.wide_words(2)
+    spec = W.wide_query(w1, w2)
+    assert np.array_equal(oracle.run(spec, {"fact": wide}, threads=threads), oracle.run(spec, {"fact": wide}))
+    dims = W.sj_dims(seed=3, scale=0.01)
+    fact = W.sj_fact(200_000, seed=3, dims=dims)
+    tables = {"lo": fact, **dims}
+    spec = W.sj_query(part_category=4, date_dow=None)
+    assert np.array_equal(oracle.run(spec, tables, threads=threads), oracle.run(spec, tables))
+    rng = np.random.default_rng(77 + threads)
+    for _ in range(6):
+        inst = _random_instance(rng, n=int(rng.integers(0, 50)))  # also fewer rows than threads
+        spec = _random_query(rng)
+        try:
+            want = oracle.run(spec, inst)
+        except oracle.OracleError as e:
+            with pytest.raises(oracle.OracleError) as e2:
+                oracle.run(spec, inst, threads=threads)
+            assert e2.value.code == e.code
+            continue
+        assert np.array_equal(oracle.run(spec, inst, threads=threads), want)
