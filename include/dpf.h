@@ -332,6 +332,28 @@ typedef struct {
 dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
                        dpf_stream stream, dpf_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the fused
+ * execution of dpf_execute with the same arguments and results, except that
+ * the launch's scratch state -- the work-queue counters and each plan's group
+ * table and status word, which dpf_execute keeps in the plans' workspaces --
+ * lives in one static device array of 8 MiB per GPU (held by the library
+ * until the process ends).  The call allocates no device or pinned memory
+ * and creates no event.  mode must be DPF_MODE_FUSED (else
+ * DPF_ERR_UNSUPPORTED).  The scratch needed is 2,304 bytes of counters plus,
+ * per plan, 256 bytes of status and ngroups x accumulators x 8 bytes of
+ * group table, each rounded up to 256 bytes; a batch needing more than
+ * 8 MiB is refused with DPF_ERR_UNSUPPORTED before anything is enqueued.  The
+ * call zeroes the part of the array it uses on the stream before its launch
+ * (the array keeps the previous call's contents).  Every call on one GPU
+ * shares that GPU's array: calls whose work overlaps on the device race and
+ * give wrong results, so order them (one stream, or events).  The records
+ * still go to each plan's pinned result buffer: synchronise the stream, then
+ * read them with dpf_result_get; release the result only after that
+ * synchronisation (it holds no completion event to wait for). */
+dpf_status dpf_execute_noalloc(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
+                               dpf_stream stream, dpf_result* out);
+
 /* Reads plan i's records after the work has completed (the caller
  * synchronises the stream).  Rows are int64: group key values, then the
  * aggregate columns, one row per non-empty group, ascending by key.  Returns

@@ -50,6 +50,7 @@ struct dpf_ctx_s {
     int64_t lds_per_block = 0;
     int64_t hbm = 0;
     std::atomic<int64_t> launches{0};
+    uint8_t* scratch = nullptr;  // this device's address of the static scratch array
 
     // Allocations up to kPoolMax (plan workspaces, result buffers, hash
     // tables, build scratch) are recycled through power-of-two size classes:
@@ -180,6 +181,40 @@ struct dpf_result_s {
 };
 
 // ---------------------------------------------------------------------------
+// Static scratch for dpf_execute_noalloc: the work-queue counters, group
+// tables and status words of one fused launch.  Every GPU holds its own copy
+// of the array at its own address until the process ends; host code uses that
+// address (from hipGetSymbolAddress), never the array's name, which on the
+// host is only a stand-in for the symbol.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+// Looked up once per device and kept.
+dpf_status static_scratch(int32_t device, uint8_t** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(DPF_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_addr[device] = (uint8_t*)p;
+    }
+    *out = g_scratch_addr[device];
+    return DPF_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
 extern "C" const char* dpf_last_error(void) { return g_err.c_str(); }
@@ -214,6 +249,11 @@ extern "C" dpf_status dpf_ctx_create(int32_t device, const dpf_allocator* alloca
                 c->lds_per_block = std::max<int64_t>(c->lds_per_block, v);
         }
         c->hbm = (int64_t)prop.totalGlobalMem;
+        dpf_status st = static_scratch(device, &c->scratch);  // hipSetDevice(device) above made it current
+        if (st != DPF_OK) {
+            delete c;
+            return st;
+        }
     }
     *out = c;
     return DPF_OK;
@@ -1412,6 +1452,44 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
         return fail(DPF_ERR_INVALID_ARG, "unknown execution mode");
     }
     return make_result(n, plans, s, true, out);
+}
+
+extern "C" dpf_status dpf_execute_noalloc(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_exec_opts* opts,
+                                          dpf_stream stream, dpf_result* out) {
+    if (!ctx || !plans || !out) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
+    dpf_status st = check_batch(ctx, n, plans);
+    if (st != DPF_OK) return st;
+    dpf_exec_opts o{};
+    o.lds_hash_bytes = -1;
+    if (opts) o = *opts;
+    if (o.mode != DPF_MODE_FUSED) return fail(DPF_ERR_UNSUPPORTED, "dpf_execute_noalloc runs the fused mode only");
+    st = check_fused_opts(n, o);
+    if (st != DPF_OK) return st;
+    if (!ctx->scratch) return fail(DPF_ERR_HIP, "no static scratch address for this device");
+    // Layout in the static array: the queue counters, then per plan a status
+    // word and the group table, each on its own 256-byte boundary.
+    FusedWorkspace ws{};
+    size_t off = align_up((size_t)kCounterWords * 4, 256);
+    ws.counters = (uint32_t*)ctx->scratch;
+    for (int i = 0; i < n; ++i) {
+        const DevQuery& q = plans[i]->hq;
+        const size_t agg_bytes = (size_t)q.ngroups * (size_t)q.nacc * 8;
+        if (agg_bytes > kStaticScratchBytes) off = kStaticScratchBytes + 1;
+        if (off > kStaticScratchBytes) break;
+        ws.status[i] = (uint32_t*)(ctx->scratch + off);
+        off += 256;
+        ws.agg[i] = (int64_t*)(ctx->scratch + off);
+        off = align_up(off + agg_bytes, 256);
+    }
+    if (off > kStaticScratchBytes)
+        return fail(DPF_ERR_UNSUPPORTED, "the plans' group tables, status words and queue counters exceed the "
+                                         "8 MiB static scratch of dpf_execute_noalloc; use dpf_execute");
+    // The array keeps the last call's contents: zero what this launch uses.
+    ws.clear = ctx->scratch;
+    ws.clear_bytes = off;
+    st = launch_fused_batch(ctx, n, plans, o, ws, (hipStream_t)stream);
+    if (st != DPF_OK) return st;
+    return make_result(n, plans, (hipStream_t)stream, false, out);
 }
 
 extern "C" dpf_status dpf_result_get(dpf_result res, int32_t i, int64_t* ngroups, int32_t* ncols, const int64_t** rows) {

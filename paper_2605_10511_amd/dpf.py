@@ -138,6 +138,7 @@ _FUNCS = {
     "dpf_plan_blocks": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dpf_plan_release": (None, [_P]),
     "dpf_execute": (C.c_int32, [_P, C.c_int32, _P, C.POINTER(dpf_exec_opts), _P, C.POINTER(_P)]),
+    "dpf_execute_noalloc": (C.c_int32, [_P, C.c_int32, _P, C.POINTER(dpf_exec_opts), _P, C.POINTER(_P)]),
     "dpf_result_get": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                    C.POINTER(C.POINTER(C.c_int64))]),
     "dpf_result_release": (None, [_P]),
@@ -491,6 +492,29 @@ def execute(ctx: Context, plans: list, mode: str = "FUSED", wg_per_cu: int = 0, 
     _check(lib.dpf_execute(ctx.h, len(plans), C.cast(arr, C.c_void_p), C.byref(o), _stream_handle(stream),
                            C.byref(h)))
     return Result(h, len(plans))
+
+
+def execute_noalloc(ctx: Context, plans: list, wg_per_cu: int = 0, rows_per_item: int = 0,
+                    lds_hash_bytes: int = -1, waves_per_wg: int = 0, max_workgroups: int = 0,
+                    stream=None) -> Result:
+    """Fused execution whose scratch state lives in the library's static
+    device array (dpf_execute_noalloc); read the result after synchronising."""
+    lib = load()
+    arr = (C.c_void_p * len(plans))(*[p.h.value for p in plans])
+    o = dpf_exec_opts(DPF_MODE_FUSED, wg_per_cu, rows_per_item, lds_hash_bytes, waves_per_wg, max_workgroups)
+    h = C.c_void_p()
+    _check(lib.dpf_execute_noalloc(ctx.h, len(plans), C.cast(arr, C.c_void_p), C.byref(o), _stream_handle(stream),
+                                   C.byref(h)))
+    return Result(h, len(plans))
+
+
+def measure_read(ctx: Context, kind: str, nbytes: int, reps: int = 10, grid: int = 0, stream=None) -> list:
+    """Per-launch milliseconds of a streaming read of nbytes from "HBM" or
+    "HOST_MAPPED" memory (dpf_measure_read)."""
+    ms = (C.c_float * reps)()
+    k = DPF_MEM_HBM if kind == "HBM" else DPF_MEM_HOST_MAPPED
+    _check(load().dpf_measure_read(ctx.h, k, int(nbytes), int(grid), int(reps), _stream_handle(stream), ms))
+    return [float(x) for x in ms]
 
 
 # ---------------------------------------------------------------------------
