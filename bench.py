@@ -214,7 +214,10 @@ def main():
     ap.add_argument("--qps", default="50,100,200,500", help="serve: arrival rates")
     ap.add_argument("--seconds", type=float, default=30.0, help="serve: run time per rate")
     ap.add_argument("--resident-rows", type=int, default=600_000_000, help="serve: resident fact rows")
-    ap.add_argument("--host-rows", type=int, default=0, help="serve: host-mapped fact rows (0: none)")
+    ap.add_argument("--host-rows", type=int, default=0, help="serve: rows of a second fact table (0: none)")
+    ap.add_argument("--residency-gb", type=float, default=16.0,
+                    help="serve: HBM residency budget for fact tables; a table beyond it rests in host memory")
+    ap.add_argument("--check-requests", type=int, default=32, help="serve: served requests checked against the oracle")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--frag-steps", type=int, default=3)
     ap.add_argument("--no-oracle", action="store_true")
@@ -416,6 +419,9 @@ def bench_prune(args):
             "aggs": [{"op": "COUNT"}, {"op": "SUM", "terms": [{"ref": {"col": "price"}}]}]}
     ctx = dpf.Context(0)
     stream = torch.cuda.current_stream()
+    ms_h = dpf.measure_read(ctx, "HOST_MAPPED", 1 << 30, reps=3)
+    host_peak = (1 << 30) / (min(ms_h) * 1e-3) / 1e9
+    log(f"[prune] measured host-mapped read peak {host_peak:.1f} GB/s")
     one_chunk = (n + 255) // 256 * 256
     runs, results = {}, []
     for placement in ("HBM", "HOST_MAPPED"):
@@ -439,7 +445,13 @@ def bench_prune(args):
             for r in rs:
                 r.release()
             key = f"{placement.lower()}_{'chunks' if chunk == 65536 else 'one_chunk'}"
-            runs[key] = {"ms": ms, "blocks_scanned": scanned, "blocks": total, "chunk_rows": chunk}
+            ref = sum(db.tables["fact"][c].info().compressed_bytes for c in referenced_columns(spec))
+            moved = ref * scanned / max(1, total)  # the referenced bytes of the blocks scanned
+            runs[key] = {"ms": ms, "blocks_scanned": scanned, "blocks": total, "chunk_rows": chunk,
+                         "scanned_bytes": moved, "gbps": moved / (ms * 1e-3) / 1e9}
+            if placement == "HOST_MAPPED":
+                runs[key]["frac_of_measured_host_read"] = runs[key]["gbps"] / host_peak
+                runs[key]["frac_of_spec_pcie"] = runs[key]["gbps"] / PCIE_PEAK_GBPS
             log(f"[prune] {placement} chunk_rows {chunk:,}: {ms:.3f} ms, {scanned}/{total} blocks scanned")
             plan.release()
             del db
@@ -458,6 +470,7 @@ def bench_prune(args):
         "config": {"workload": f"chunk pruning: date-range filter-aggregate ({n:,} date-clustered rows, 10% of "
                                f"the dates), 65,536-row chunks vs one chunk", "rows": n},
         "runs": runs,
+        "measured_host_read_gbps": host_peak,
         "speedup_hbm": runs["hbm_one_chunk"]["ms"] / hbm,
         "speedup_host_mapped": runs["host_mapped_one_chunk"]["ms"] / runs["host_mapped_chunks"]["ms"],
         "results_equal": same, "parity_vs_oracle": parity,
@@ -744,7 +757,7 @@ def bench_serve(args):
     import oracle
     from datagen import workloads as W
     from paper_2605_10511_amd import dpf
-    from paper_2605_10511_amd.serve import Request, Server, latency_stats
+    from paper_2605_10511_amd.serve import Request, Server, latency_stats, place_table
 
     rates = [float(x) for x in str(args.qps).split(",") if x]
     dims = W.sj_dims(seed=3)
@@ -753,20 +766,21 @@ def bench_serve(args):
     t0 = time.time()
     for name, cols in dims.items():
         db.add_table(name, cols)
+    budget = int(args.residency_gb * 1e9)
     res = W.union_table(args.resident_rows, seed=5, dims=dims)
-    db.add_table("res", res, W.FA_ENCODINGS, placement="HBM")
+    res_place = place_table(db, "res", res, W.FA_ENCODINGS, budget)
     res_bytes = sum(c.info().compressed_bytes for c in db.tables["res"].values())
-    log(f"[serve] resident table {args.resident_rows:,} rows, {res_bytes / 1e9:.2f} GB compressed, "
+    log(f"[serve] resident table {args.resident_rows:,} rows, {res_bytes / 1e9:.2f} GB compressed -> {res_place}, "
         f"built in {time.time() - t0:.1f} s")
-    host = None
+    host_place = None
     if args.host_rows > 0:
         t1 = time.time()
         host = W.union_table(args.host_rows, seed=55, dims=dims)
-        db.add_table("host", host, W.FA_ENCODINGS, placement="HOST_MAPPED")
+        host_place = place_table(db, "host", host, W.FA_ENCODINGS, budget)
         host_bytes = sum(c.info().compressed_bytes for c in db.tables["host"].values())
-        log(f"[serve] host-mapped table {args.host_rows:,} rows, {host_bytes / 1e9:.2f} GB, "
-            f"built in {time.time() - t1:.1f} s")
-        del host  # the pinned copy is the table now
+        log(f"[serve] second table {args.host_rows:,} rows, {host_bytes / 1e9:.2f} GB -> {host_place} "
+            f"(residency budget {budget / 1e9:.0f} GB), built in {time.time() - t1:.1f} s")
+        del host  # the encoded copy is the table now
 
     def alg_bytes(spec):
         t = db.tables[spec["fact"]]
@@ -776,8 +790,13 @@ def bench_serve(args):
                  if "ref" in tm and "col" in tm["ref"]]
         return sum(t[c].info().compressed_bytes for c in dict.fromkeys(used))
 
-    srv = Server(ctx, db, nstreams=4, slots=8, state_budget=4 << 30,
-                 host_tables=("host",) if args.host_rows > 0 else ())
+    host_peak = None
+    if args.host_rows > 0:
+        ms = dpf.measure_read(ctx, "HOST_MAPPED", 1 << 30, reps=3)
+        host_peak = (1 << 30) / (min(ms) * 1e-3) / 1e9
+        log(f"[serve] measured host-mapped read peak {host_peak:.1f} GB/s (spec {PCIE_PEAK_GBPS:.0f} GB/s)")
+    srv = Server(ctx, db, nstreams=4, slots=8, state_budget=4 << 30)
+    log(f"[serve] tables read over the host link: {sorted(srv.host_tables)}")
     # warm, untimed: a burst of 48 resident requests (and 2 host-table ones)
     # fills the memory pool's size classes and loads every code path
     warm = [Request(0.0, k, sp, "res") for _, k, sp in W.serve_requests(99, 1000.0, 0.048, "res", stream="warm")]
@@ -810,14 +829,28 @@ def bench_serve(args):
         row = {"lambda_qps": lam, "offered": len(reqs), "wall_s": wall, "resident": st_res,
                "hbm_gbps": moved / span / 1e9, "host_mapped": st_host if args.host_rows > 0 else None,
                "host_link_gbps": hmoved / span / 1e9 if args.host_rows > 0 else None}
+        if args.host_rows > 0:
+            # the link's share while host-table scans ran: bytes over the scans' own service time
+            hs = [r for r in done if r.table == "host"]
+            busy = sum(r.done - r.issued for r in hs)
+            row["host_scan_gbps"] = hmoved / busy / 1e9 if busy > 0 else None
+            row["host_scan_frac_of_measured_peak"] = (row["host_scan_gbps"] / host_peak) if busy > 0 else None
+            row["host_scan_frac_of_spec_pcie"] = (row["host_scan_gbps"] / PCIE_PEAK_GBPS) if busy > 0 else None
         per_rate.append(row)
         log(f"[serve] lambda {lam:g}: {st_res['completed']} done, {st_res['qps']:.1f} QPS, "
             f"p50 {st_res.get('p50_ms', 0):.2f} ms, p99 {st_res.get('p99_ms', 0):.2f} ms, "
             f"{row['hbm_gbps']:.0f} GB/s")
-        if not sample:
-            fa = [r for r in done if r.table == "res" and r.template == "FA"][:8]
-            sj = [r for r in done if r.table == "res" and r.template == "SJ"][:8]
-            sample = fa + sj
+        if not sample:  # distinct served requests of both templates from the first rate
+            half = max(1, args.check_requests // 2)
+            seen = set()
+            for tmpl in ("FA", "SJ"):
+                k = 0
+                for r in done:
+                    key = json.dumps(r.spec, sort_keys=True, default=str)
+                    if r.table == "res" and r.template == tmpl and key not in seen and k < half:
+                        seen.add(key)
+                        sample.append(r)
+                        k += 1
 
     # alone-vs-mix: each sampled request again, alone, must give the same rows
     alone_eq = True
@@ -834,18 +867,28 @@ def bench_serve(args):
     cpu = None
     parity = None
     if not args.no_oracle and sample:
-        chk = [sample[0], sample[len(sample) // 2]]
-        tables = {"res": res, **dims}
+        # the oracle reads int64 columns: widen each referenced column once
+        used = sorted({c for r in sample for c in referenced_columns(r.spec)})
+        res64 = {c: np.ascontiguousarray(res[c], dtype=np.int64) for c in used}
+        for c in list(res):
+            del res[c]
+        tables = {"res": res64, **dims}
+        nt = host_threads()
         t2 = time.perf_counter()
-        with cf.ThreadPoolExecutor(max_workers=2) as ex:
-            want = list(ex.map(lambda r: oracle.run(r.spec, tables), chk))
+        bad = []
+        for i, r in enumerate(sample):
+            if not np.array_equal(oracle.run(r.spec, tables, threads=nt), r.rows):
+                bad.append(i)
         ot = time.perf_counter() - t2
-        parity = all(np.array_equal(w, r.rows) for w, r in zip(want, chk))
-        nrows = args.resident_rows * len(chk)
-        cpu = {"value": nrows / ot, "unit": "rows/s", "cores": 2, "kind": "oracle",
-               "sample": f"two served requests (one FA, one SJ) re-evaluated on the "
-                         f"{args.resident_rows:,}-row resident table, one thread each ({ot:.1f} s)"}
-        log(f"[serve] oracle on 2 requests {ot:.1f} s: {'==' if parity else '!='}")
+        parity = not bad
+        nrows = args.resident_rows * len(sample)
+        cpu = {"value": nrows / ot, "unit": "rows/s", "cores": nt, "kind": "oracle",
+               "sample": f"{len(sample)} distinct served requests ({sum(r.template == 'FA' for r in sample)} FA, "
+                         f"{sum(r.template == 'SJ' for r in sample)} SJ) re-evaluated on the "
+                         f"{args.resident_rows:,}-row resident table, rows split over {nt} threads ({ot:.1f} s)",
+               "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+        log(f"[serve] oracle on {len(sample)} served requests {ot:.1f} s: "
+            f"{'all ==' if parity else f'{len(bad)} differ'}")
     srv.close()
 
     top = per_rate[-1]["resident"] if per_rate else {}
@@ -870,9 +913,12 @@ def bench_serve(args):
                    "host_table_knobs": srv.host_knobs,
                    "resident_compressed_bytes": res_bytes},
         "rates": per_rate,
+        "measured_host_read_gbps": host_peak,
         "hash_builds": srv.hash_builds,
         "hash_build_seconds": srv.hash_build_s,
         "alone_equals_served": alone_eq,
+        "checked_requests": len(sample),
+        "placements": {"res": res_place, "host": host_place, "residency_budget_bytes": budget},
         "roofline": {"bound": "hbm", "achieved": per_rate[-1]["hbm_gbps"] if per_rate else None,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": (per_rate[-1]["hbm_gbps"] / HBM_PEAK_GBPS) if per_rate else None,

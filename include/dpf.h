@@ -69,7 +69,9 @@ enum { DPF_MEM_HBM = 0, DPF_MEM_HOST_MAPPED = 1 };
 /* Optional allocator.  alloc returns memory of the given kind (HBM, or pinned
  * host memory that the device can address) or NULL; free releases it.  For
  * DPF_MEM_HOST_MAPPED the returned pointer must be a host pointer that
- * hipHostGetDevicePointer accepts. */
+ * hipHostGetDevicePointer accepts.  The library synchronises the device
+ * before it hands a block back through free (it does not track which
+ * streams used the block). */
 typedef struct {
     void* user;
     void* (*alloc)(void* user, size_t bytes, int32_t kind);
@@ -225,11 +227,13 @@ typedef struct {
 dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf_stream stream, dpf_hash* out);
 
 typedef struct {
-    int64_t entries, capacity, bytes;
+    int64_t entries, capacity, bytes;  /* bytes: keys and payloads (what an LDS copy takes) */
     int32_t lds_eligible, placement;
     int32_t npayloads;
     int64_t key_min, key_max;
     int64_t payload_min[2], payload_max[2];
+    int64_t device_bytes;              /* the table's device allocation: keys, payloads,
+                                          membership bitmap and bit filter */
 } dpf_hash_stats;
 dpf_status dpf_hash_info(dpf_hash h, dpf_hash_stats* out);
 void dpf_hash_release(dpf_hash h);
@@ -283,11 +287,20 @@ typedef struct {
 /* Validates the plan, proves every aggregate stays within int64 over the
  * table (else DPF_ERR_OVERFLOW), sizes the group table and pre-allocates the
  * per-plan device workspace and pinned result buffer, so that executing the
- * plan allocates nothing and can be captured in a HIP graph. */
+ * plan allocates nothing and can be captured in a HIP graph.  The device
+ * copy of the plan (its descriptor, the surviving-block list and the zeroed
+ * workspace) is enqueued on the context's own upload stream from pinned
+ * staging, and the call returns without waiting for it: every execution
+ * orders itself after that upload (a stream wait on its event, or a host
+ * wait when the execution is being captured into a graph). */
 dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf_plan* out);
 
-/* Device memory the plan itself holds (group table, workspace and the hash
- * tables it probes), for admission control. */
+/* Device memory the plan itself holds, for admission control: its workspace
+ * (descriptor, group table, status word, queue counters, surviving-block
+ * list) and, once it has run fragmented, that path's intermediate buffers.
+ * The dimension hash tables it probes belong to their own handles and are
+ * not counted (dpf_hash_stats.device_bytes gives them), so that a table many
+ * plans share is charged once. */
 dpf_status dpf_plan_footprint(dpf_plan plan, size_t* hbm_bytes);
 
 /* Chunk pruning (paper Section 3.1.1: predicates checked against zone maps

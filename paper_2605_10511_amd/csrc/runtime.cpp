@@ -51,6 +51,7 @@ struct dpf_ctx_s {
     int64_t hbm = 0;
     std::atomic<int64_t> launches{0};
     uint8_t* scratch = nullptr;  // this device's address of the static scratch array
+    hipStream_t upload = nullptr;  // plan uploads (non-blocking, default priority)
 
     // Allocations up to kPoolMax (plan workspaces, result buffers, hash
     // tables, build scratch) are recycled through power-of-two size classes:
@@ -74,7 +75,13 @@ struct dpf_ctx_s {
         return p;
     }
     void raw_free(void* p, int kind) {
-        if (custom) { alloc.free(alloc.user, p, kind); return; }
+        if (custom) {
+            // the caller's allocator may hand the block out again at once:
+            // no kernel may still be reading it
+            if (device >= 0) (void)hipDeviceSynchronize();
+            alloc.free(alloc.user, p, kind);
+            return;
+        }
         if (kind == DPF_MEM_HBM) (void)hipFree(p);
         else (void)hipHostFree(p);
     }
@@ -113,6 +120,7 @@ struct dpf_ctx_s {
     }
     ~dpf_ctx_s() {
         if (device >= 0) (void)hipDeviceSynchronize();
+        if (upload) (void)hipStreamDestroy(upload);
         for (auto& kv : pooled) raw_free(kv.first, kv.second.first);
     }
     void* device_ptr(void* host) {  // device address of pinned host memory
@@ -166,10 +174,17 @@ struct dpf_plan_s {
     int32_t lds_budget = -2;
     int32_t naggs_out = 0;
     bool issued = false;
+    // The descriptor, block list and zeroed workspace go to the device on the
+    // context's upload stream from this pinned staging copy; executions wait
+    // for `uploaded` while `upload_pending`.
+    void* staging = nullptr;
+    hipEvent_t uploaded = nullptr;
+    bool upload_pending = false;
     // fragmented execution buffers
     bool frag_ready = false;
     FragBuffers fb{};
     std::vector<void*> frag_allocs;
+    size_t frag_bytes = 0;
 };
 
 struct dpf_result_s {
@@ -253,6 +268,12 @@ extern "C" dpf_status dpf_ctx_create(int32_t device, const dpf_allocator* alloca
         if (st != DPF_OK) {
             delete c;
             return st;
+        }
+        e = hipStreamCreateWithFlags(&c->upload, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            c->upload = nullptr;
+            delete c;
+            return hip_fail(e, "hipStreamCreateWithFlags(upload)");
         }
     }
     *out = c;
@@ -787,6 +808,7 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     st.capacity = (int64_t)cap;
     st.bytes = (int64_t)bytes;
     st.lds_eligible = bytes <= 96 * 1024;
+    st.device_bytes = (int64_t)alloc_bytes;
     st.placement = desc->placement;
     st.npayloads = A.npay;
     st.key_min = count ? mm[0] : 0;
@@ -888,6 +910,7 @@ __int128 term_bound(int64_t mul, int64_t add, int64_t lo, int64_t hi) {
 void free_frag(dpf_plan p) {
     for (void* a : p->frag_allocs) p->ctx->free_mem(a, DPF_MEM_HBM);
     p->frag_allocs.clear();
+    p->frag_bytes = 0;
     p->frag_ready = false;
 }
 }  // namespace
@@ -1179,10 +1202,30 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     q.live = prune_mb ? (const int32_t*)(d + live_off) : nullptr;
     q.nlive = (int32_t)live.size();
     q.prune_mb = prune_mb;
-    hipError_t e = hipMemset(d + agg_off, 0, live_off - agg_off);
-    if (e == hipSuccess && !live.empty()) e = hipMemcpy(d + live_off, live.data(), live.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->dq, &q, sizeof q, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return bail(hip_fail(e, "plan upload"));
+    // Asynchronous upload on the context's upload stream: a fill kernel
+    // zeroes the group table, status and queue counters, and the descriptor
+    // and block list are copied from pinned staging.  The first executions
+    // wait for the event (see wait_uploads); nothing here blocks the host.
+    const size_t stage_q = align_up(sizeof(DevQuery), 256);
+    p->staging = ctx->alloc_mem(stage_q + live.size() * 4, DPF_MEM_HOST_MAPPED);
+    if (!p->staging) return bail(fail(DPF_ERR_OOM, "plan staging"));
+    std::memcpy(p->staging, &q, sizeof q);
+    if (!live.empty()) std::memcpy((uint8_t*)p->staging + stage_q, live.data(), live.size() * 4);
+    hipError_t e = launch_fill_i32((int32_t*)(d + agg_off), 0, (int64_t)((live_off - agg_off) / 4), ctx->upload);
+    if (e == hipSuccess && !live.empty())
+        e = hipMemcpyAsync(d + live_off, (uint8_t*)p->staging + stage_q, live.size() * 4, hipMemcpyHostToDevice,
+                           ctx->upload);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->dq, p->staging, sizeof q, hipMemcpyHostToDevice, ctx->upload);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(p->uploaded, ctx->upload);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(ctx->upload);
+        if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+        ctx->free_mem(p->staging, DPF_MEM_HOST_MAPPED);
+        return bail(hip_fail(e, "plan upload"));
+    }
+    p->upload_pending = true;
+    ctx->launches++;
 
     for (int i = 0; i < desc->ncols; ++i) { desc->cols[i]->refs++; p->cols.push_back(desc->cols[i]); }
     for (int j = 0; j < desc->nprobes; ++j) { desc->probes[j].hash->refs++; p->hashes.push_back(desc->probes[j].hash); }
@@ -1192,8 +1235,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
 
 extern "C" dpf_status dpf_plan_footprint(dpf_plan plan, size_t* hbm_bytes) {
     if (!plan || !hbm_bytes) return fail(DPF_ERR_INVALID_ARG, "NULL argument");
-    size_t b = plan->dmem_bytes;
-    for (dpf_hash h : plan->hashes) b += h->bytes;
+    size_t b = plan->dmem_bytes + plan->frag_bytes;
     *hbm_bytes = b;
     return DPF_OK;
 }
@@ -1208,6 +1250,11 @@ extern "C" dpf_status dpf_plan_blocks(dpf_plan plan, int64_t* scanned_blocks, in
 extern "C" void dpf_plan_release(dpf_plan plan) {
     if (!plan) return;
     if (--plan->refs > 0) return;
+    if (plan->uploaded) {
+        (void)hipEventSynchronize(plan->uploaded);  // the staging copy may still be read
+        (void)hipEventDestroy(plan->uploaded);
+    }
+    if (plan->staging) plan->ctx->free_mem(plan->staging, DPF_MEM_HOST_MAPPED);
     free_frag(plan);
     plan->ctx->free_mem(plan->dmem, DPF_MEM_HBM);
     plan->ctx->free_mem(plan->host_out, DPF_MEM_HOST_MAPPED);
@@ -1226,7 +1273,10 @@ dpf_status ensure_frag(dpf_plan p) {
     dpf_ctx ctx = p->ctx;
     auto get = [&](size_t bytes) -> void* {
         void* a = ctx->alloc_mem(bytes, DPF_MEM_HBM);
-        if (a) p->frag_allocs.push_back(a);
+        if (a) {
+            p->frag_allocs.push_back(a);
+            p->frag_bytes += bytes;
+        }
         return a;
     };
     FragBuffers& fb = p->fb;
@@ -1280,6 +1330,32 @@ struct FusedWorkspace {
     void* clear;
     size_t clear_bytes;
 };
+
+// Orders each plan's execution after its upload: an upload still in flight
+// is waited for on the stream (or, under stream capture, on the host, since
+// a captured graph cannot depend on work outside it).  Once the event has
+// completed the plan needs no wait again.
+dpf_status wait_uploads(int32_t n, const dpf_plan* plans, hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    bool capturing = false;
+    for (int i = 0; i < n; ++i) {
+        dpf_plan p = plans[i];
+        if (!p->upload_pending) continue;
+        if (hipEventQuery(p->uploaded) == hipSuccess) {
+            p->upload_pending = false;
+            continue;
+        }
+        if (!capturing && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            capturing = true;
+        if (capturing) {
+            HIP_TRY(hipEventSynchronize(p->uploaded));
+            p->upload_pending = false;
+        } else {
+            HIP_TRY(hipStreamWaitEvent(s, p->uploaded, 0));
+        }
+    }
+    return DPF_OK;
+}
 
 dpf_status check_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans) {
     if (ctx->device < 0) return fail(DPF_ERR_INVALID_ARG, "execution needs a device context");
@@ -1426,6 +1502,8 @@ extern "C" dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans,
     o.lds_hash_bytes = -1;
     if (opts) o = *opts;
     hipStream_t s = (hipStream_t)stream;
+    st = wait_uploads(n, plans, s);
+    if (st != DPF_OK) return st;
     if (o.mode == DPF_MODE_FRAGMENTED) {
         for (int i = 0; i < n; ++i) {
             dpf_plan p = plans[i];
@@ -1484,6 +1562,8 @@ extern "C" dpf_status dpf_execute_noalloc(dpf_ctx ctx, int32_t n, const dpf_plan
     if (off > kStaticScratchBytes)
         return fail(DPF_ERR_UNSUPPORTED, "the plans' group tables, status words and queue counters exceed the "
                                          "8 MiB static scratch of dpf_execute_noalloc; use dpf_execute");
+    st = wait_uploads(n, plans, (hipStream_t)stream);
+    if (st != DPF_OK) return st;
     // The array keeps the last call's contents: zero what this launch uses.
     ws.clear = ctx->scratch;
     ws.clear_bytes = off;

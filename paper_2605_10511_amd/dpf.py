@@ -87,7 +87,8 @@ class dpf_hash_stats(C.Structure):
     _fields_ = [("entries", C.c_int64), ("capacity", C.c_int64), ("bytes", C.c_int64),
                 ("lds_eligible", C.c_int32), ("placement", C.c_int32), ("npayloads", C.c_int32),
                 ("key_min", C.c_int64), ("key_max", C.c_int64),
-                ("payload_min", C.c_int64 * 2), ("payload_max", C.c_int64 * 2)]
+                ("payload_min", C.c_int64 * 2), ("payload_max", C.c_int64 * 2),
+                ("device_bytes", C.c_int64)]
 
 
 class dpf_ref(C.Structure):
@@ -219,9 +220,11 @@ class TorchAllocator:
 
 
 class Context:
-    """A library context on one GPU (device=-1: host-only encoding)."""
+    """A library context on one GPU (device=-1: host-only encoding).  By
+    default its device memory comes from torch's caching allocator and its
+    pinned host memory from torch's pinned-memory allocator."""
 
-    def __init__(self, device: int = 0, torch_allocator: bool = False):
+    def __init__(self, device: int = 0, torch_allocator: bool = True):
         lib = load()
         self._alloc = TorchAllocator(device) if (torch_allocator and device >= 0) else None
         h = C.c_void_p()

@@ -6,9 +6,10 @@ Requests arrive over time (Poisson in the benchmark).  The server
   keyed by (dimension, key, filter, payloads) and are built once, on the
   device (paper Section 3.1, Kernel #1); the plan is compiled against the
   resident fact columns;
-* admits prepared requests while their device state (plan workspace plus
-  the hash tables they hold, ``dpf_plan_footprint``) fits the state budget
-  and an in-flight slot is free;
+* admits prepared requests while the device state fits the state budget:
+  the in-flight plans' own workspaces (``dpf_plan_footprint``) plus the
+  cached dimension hash tables, each charged once however many plans probe
+  it; an in-flight slot must also be free;
 * batches whatever is admitted into ONE fused launch per free stream
   (continuous batching: a new batch starts as soon as a stream drains, it
   does not wait for a full batch), so queries that arrive together share a
@@ -16,9 +17,10 @@ Requests arrive over time (Poisson in the benchmark).  The server
 * completes a batch when its stream event fires, decodes the records and
   records arrival-to-result latency.
 
-Tables larger than the residency budget are placed in pinned host memory
-mapped into the device and scanned over the host link (Section 3.1's zero
-copy path).  Requests on such tables run on a stream of their own and never
+``place_table`` decides where a table rests: in HBM while the tables placed
+so far and this one fit the residency budget, otherwise in pinned host
+memory mapped into the device, scanned over the host link (Section 3.1's
+zero-copy path).  The server finds such tables by their columns' placement.  Requests on such tables run on a stream of their own and never
 share a batch with resident-table requests: a launch finishes when its
 slowest plan does, and a host-link scan takes tens of milliseconds.  They
 also run with one workgroup per CU (``host_knobs``): the host link, not the
@@ -57,7 +59,7 @@ class _Batch:
 
 class Server:
     def __init__(self, ctx: dpf.Context, db: dpf.Database, nstreams: int = 4, slots: int = 8,
-                 state_budget: int = 4 << 30, placements: dict | None = None, host_tables=(),
+                 state_budget: int = 4 << 30, placements: dict | None = None, host_tables=None,
                  host_knobs: dict | None = None, max_batch: int = 64):
         import torch
         self.torch = torch
@@ -70,6 +72,10 @@ class Server:
         self.placements = placements or {}
         self.hash_builds = 0
         self.hash_build_s = 0.0
+        self.hash_bytes = 0  # device bytes of the cached hash tables, charged once
+        if host_tables is None:  # the tables whose columns rest in host memory
+            host_tables = [t for t, cols in db.tables.items()
+                           if cols and next(iter(cols.values())).info().placement == dpf.DPF_PLACE_HOST_MAPPED]
         self.host_tables = set(host_tables)
         self.host_knobs = dict(host_knobs) if host_knobs is not None else {"max_workgroups": 64}
         self.host_stream = torch.cuda.Stream() if self.host_tables else None  # default priority
@@ -93,6 +99,7 @@ class Server:
                          self.placements.get(pr["dim"], "AUTO"), s)
             s.synchronize()  # later batches on other streams read it
             self.hashes[key] = h
+            self.hash_bytes += h.info().device_bytes
             self.hash_builds += 1
             self.hash_build_s += time.perf_counter() - t0
         return h
@@ -160,7 +167,7 @@ class Server:
                 fp = 0
                 while ready and nin + len(batch) < self.slots and len(batch) < self.max_batch:
                     r = ready[0]
-                    if used + fp + r.footprint > self.state_budget and (batch or inflight):
+                    if used + self.hash_bytes + fp + r.footprint > self.state_budget and (batch or inflight):
                         break  # wait for state to drain
                     batch.append(ready.popleft())
                     fp += r.footprint
@@ -217,7 +224,36 @@ class Server:
         for h in self.hashes.values():
             h.release()
         self.hashes.clear()
+        self.hash_bytes = 0
         self.host_stream = None
+
+
+def place_table(db: dpf.Database, name: str, columns: dict, encodings: dict | None, residency_budget: int,
+                chunk_rows: int = 65536, sample_rows: int = 1 << 20) -> str:
+    """Encode a table where the residency budget allows: HBM when the
+    compressed bytes of the tables already resident in HBM plus this one fit
+    ``residency_budget``, else pinned host memory mapped into the device.
+    The table's compressed size is estimated from its first ``sample_rows``
+    rows, encoded on the host with the same encodings.  Returns the
+    placement chosen ("HBM" or "HOST_MAPPED")."""
+    n = len(next(iter(columns.values())).offsets) - 1 if hasattr(next(iter(columns.values())), "offsets") \
+        else len(next(iter(columns.values())))
+    k = min(n, sample_rows)
+    host_ctx = dpf.Context(-1)
+    est = 0
+    enc = encodings or {}
+    for c, v in columns.items():
+        part = v[:k] if not hasattr(v, "offsets") else type(v)(v.offsets[:k + 1], v.data[:int(v.offsets[k])])
+        col = dpf.Column(host_ctx, part, enc.get(c, "AUTO"), chunk_rows, "HOST")
+        est += col.info().compressed_bytes
+        col.release()
+    host_ctx.close()
+    est = int(est * (n / max(1, k)))
+    resident = sum(col.info().compressed_bytes for t in db.tables.values() for col in t.values()
+                   if col.info().placement == dpf.DPF_PLACE_HBM)
+    placement = "HBM" if resident + est <= residency_budget else "HOST_MAPPED"
+    db.add_table(name, columns, encodings, chunk_rows=chunk_rows, placement=placement)
+    return placement
 
 
 def latency_stats(done: list, seconds: float) -> dict:
