@@ -52,9 +52,13 @@ class _Pred(C.Structure):
 
 
 class _Probe(C.Structure):
-    _fields_ = [("cols", C.c_void_p), ("ncols", C.c_int32), ("key_col", C.c_int32),
-                ("preds", C.c_void_p), ("npreds", C.c_int32), ("npay", C.c_int32),
-                ("pay_col", C.c_int32 * MAX_PAYLOADS), ("fact_fk_col", C.c_int32)]
+    pass
+
+
+_Probe._fields_ = [("cols", C.c_void_p), ("ncols", C.c_int32), ("key_col", C.c_int32),
+                   ("preds", C.c_void_p), ("npreds", C.c_int32), ("npay", C.c_int32),
+                   ("pay_col", C.c_int32 * MAX_PAYLOADS), ("fact_fk_col", C.c_int32),
+                   ("pay_src", C.c_int32 * MAX_PAYLOADS), ("sub", C.c_void_p), ("nsub", C.c_int32)]
 
 
 class _Ref(C.Structure):
@@ -171,16 +175,11 @@ def _ref(r: dict, index: dict) -> _Ref:
     return _Ref(int(r["probe"]), int(r["payload"]))
 
 
-def run(spec: dict, tables: dict, threads: int = 1) -> np.ndarray:
-    """Evaluate a query description over uncompressed tables; returns the
-    (ngroups, ncols) int64 result, ascending by group key.  threads > 1 runs
-    the timing-only variant that splits the fact rows over that many host
-    threads (same records)."""
-    lib = _load()
-    keep = _Keep()
-    fact = tables[spec["fact"]]
-    fcols, findex = _columns(fact, keep)
-    probes = spec.get("probes", [])
+def _probe_array(probes: list, parent_index: dict, tables: dict, keep: _Keep):
+    """The probes of one table (the fact table, or a joined dimension) as an
+    array of _Probe; a probe's own "probes" describe its joined build side,
+    and a payload {"probe": j, "payload": k} takes payload k of that side's
+    probe j."""
     if len(probes) > MAX_PROBES:
         raise OracleError(ERR_INVALID)
     parr = (_Probe * max(1, len(probes)))()
@@ -197,8 +196,33 @@ def run(spec: dict, tables: dict, threads: int = 1) -> np.ndarray:
             raise OracleError(ERR_INVALID)
         parr[j].npay = len(pays)
         for k, pc in enumerate(pays):
-            parr[j].pay_col[k] = dindex[pc]
-        parr[j].fact_fk_col = findex[pr["fk"]]
+            if isinstance(pc, dict):
+                parr[j].pay_src[k] = int(pc["probe"])
+                parr[j].pay_col[k] = int(pc["payload"])
+            else:
+                parr[j].pay_src[k] = -1
+                parr[j].pay_col[k] = dindex[pc]
+        parr[j].fact_fk_col = parent_index[pr["fk"]]
+        subs = pr.get("probes", [])
+        if subs:
+            sarr = _probe_array(subs, dindex, tables, keep)
+            parr[j].sub = C.cast(sarr, C.c_void_p)
+            parr[j].nsub = len(subs)
+    keep.objs.append(parr)
+    return parr
+
+
+def run(spec: dict, tables: dict, threads: int = 1) -> np.ndarray:
+    """Evaluate a query description over uncompressed tables; returns the
+    (ngroups, ncols) int64 result, ascending by group key.  threads > 1 runs
+    the timing-only variant that splits the fact rows over that many host
+    threads (same records)."""
+    lib = _load()
+    keep = _Keep()
+    fact = tables[spec["fact"]]
+    fcols, findex = _columns(fact, keep)
+    probes = spec.get("probes", [])
+    parr = _probe_array(probes, findex, tables, keep)
     keys = spec.get("group_by", [])
     karr = (_Ref * max(1, len(keys)))(*[_ref(r, findex) for r in keys])
     aggs = spec.get("aggs", [])

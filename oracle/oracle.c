@@ -103,28 +103,64 @@ static int cmp_entry(const void* a, const void* b) {
 
 typedef struct { dim_entry* e; int64_t n; } dim_map;
 
-static int build_dim(const orc_probe* pr, dim_map* out) {
+static const dim_entry* probe_dim(const dim_map* m, int64_t key) {
+    dim_entry k;
+    k.key = key;
+    return (const dim_entry*)bsearch(&k, m->e, (size_t)m->n, sizeof(dim_entry), cmp_entry);
+}
+
+#define ORC_MAX_DEPTH 4  /* nesting of joined build sides */
+
+/* The qualifying rows of a (possibly joined) dimension, sorted by key: a row
+ * qualifies if it passes the dimension's predicates and, for each of its own
+ * probes, its foreign key is a key of that probe's qualifying rows (built
+ * first, the same way: a filtered inner join, Section 3.1's Kernel #2). */
+static int build_dim_at(const orc_probe* pr, dim_map* out, int depth) {
     const orc_column* cols = pr->cols;
+    if (depth > ORC_MAX_DEPTH || pr->nsub < 0 || pr->nsub > ORC_MAX_PROBES || (pr->nsub && !pr->sub))
+        return ORC_ERR_INVALID;
     if (pr->key_col < 0 || pr->key_col >= pr->ncols || !cols[pr->key_col].ival) return ORC_ERR_INVALID;
     if (pr->npay < 0 || pr->npay > ORC_MAX_PAYLOADS) return ORC_ERR_INVALID;
-    for (int32_t k = 0; k < pr->npay; ++k)
-        if (pr->pay_col[k] < 0 || pr->pay_col[k] >= pr->ncols || !cols[pr->pay_col[k]].ival)
+    for (int32_t k = 0; k < pr->npay; ++k) {
+        const int32_t src = pr->nsub ? pr->pay_src[k] : -1;
+        if (src < 0 && (pr->pay_col[k] < 0 || pr->pay_col[k] >= pr->ncols || !cols[pr->pay_col[k]].ival))
+            return ORC_ERR_INVALID;
+        if (src >= 0 && (src >= pr->nsub || pr->pay_col[k] < 0 || pr->pay_col[k] >= pr->sub[src].npay))
+            return ORC_ERR_INVALID;
+    }
+    for (int32_t j = 0; j < pr->nsub; ++j)
+        if (pr->sub[j].fact_fk_col < 0 || pr->sub[j].fact_fk_col >= pr->ncols || !cols[pr->sub[j].fact_fk_col].ival)
             return ORC_ERR_INVALID;
     int rc = check_preds(pr->preds, pr->npreds, cols, pr->ncols);
     if (rc) return rc;
+    dim_map sub[ORC_MAX_PROBES];
+    memset(sub, 0, sizeof sub);
+    for (int32_t j = 0; j < pr->nsub && !rc; ++j) rc = build_dim_at(&pr->sub[j], &sub[j], depth + 1);
     int64_t nrows = cols[pr->key_col].nrows;
-    dim_entry* e = (dim_entry*)malloc((size_t)(nrows > 0 ? nrows : 1) * sizeof(dim_entry));
-    if (!e) return ORC_ERR_OOM;
+    dim_entry* e = rc ? NULL : (dim_entry*)malloc((size_t)(nrows > 0 ? nrows : 1) * sizeof(dim_entry));
+    if (!rc && !e) rc = ORC_ERR_OOM;
     int64_t n = 0;
-    for (int64_t r = 0; r < nrows; ++r) {
+    const dim_entry* hit[ORC_MAX_PROBES];
+    for (int64_t r = 0; r < nrows && !rc; ++r) {
         int ok = 1;
         for (int32_t i = 0; i < pr->npreds && ok; ++i) ok = eval_pred(&pr->preds[i], cols, r);
+        for (int32_t j = 0; j < pr->nsub && ok; ++j) {
+            hit[j] = probe_dim(&sub[j], cols[pr->sub[j].fact_fk_col].ival[r]);
+            ok = hit[j] != NULL;
+        }
         if (!ok) continue;
         e[n].key = cols[pr->key_col].ival[r];
-        for (int32_t k = 0; k < ORC_MAX_PAYLOADS; ++k)
+        for (int32_t k = 0; k < ORC_MAX_PAYLOADS; ++k) {
+            if (k < pr->npay && pr->nsub && pr->pay_src[k] >= 0) {
+                e[n].pay[k] = hit[pr->pay_src[k]]->pay[pr->pay_col[k]];
+                continue;
+            }
             e[n].pay[k] = k < pr->npay ? cols[pr->pay_col[k]].ival[r] : 0;
+        }
         ++n;
     }
+    for (int32_t j = 0; j < pr->nsub; ++j) free(sub[j].e);
+    if (rc) { free(e); return rc; }
     qsort(e, (size_t)n, sizeof(dim_entry), cmp_entry);
     for (int64_t i = 1; i < n; ++i)
         if (e[i].key == e[i - 1].key) { free(e); return ORC_ERR_DUPLICATE; }
@@ -133,11 +169,7 @@ static int build_dim(const orc_probe* pr, dim_map* out) {
     return ORC_OK;
 }
 
-static const dim_entry* probe_dim(const dim_map* m, int64_t key) {
-    dim_entry k;
-    k.key = key;
-    return (const dim_entry*)bsearch(&k, m->e, (size_t)m->n, sizeof(dim_entry), cmp_entry);
-}
+static int build_dim(const orc_probe* pr, dim_map* out) { return build_dim_at(pr, out, 0); }
 
 /* ------------------------------------------------------------------------ */
 /* Group store: records [key_0 .. key_{nk-1}, acc_0 .. acc_{na-1}] kept in    */

@@ -41,8 +41,14 @@ typedef struct {
 } orc_pred;
 
 /* An inner join of fact column fact_fk_col with the key of a filtered
- * dimension; the dimension's keys must be unique among qualifying rows. */
-typedef struct {
+ * dimension; the dimension's keys must be unique among qualifying rows.
+ * The dimension may itself be joined (a build side that is a pipeline, as
+ * in the paper's Section 3.1 running example): its rows qualify only if they
+ * pass preds and find a match in every one of its nsub own probes sub[]
+ * (whose fact_fk_col names a column of this dimension).  Payload k is column
+ * pay_col[k] of this dimension when pay_src[k] < 0, else payload pay_col[k]
+ * of sub-probe pay_src[k]. */
+typedef struct orc_probe_s {
     const orc_column* cols;
     int32_t ncols;
     int32_t key_col;
@@ -51,6 +57,9 @@ typedef struct {
     int32_t npay;
     int32_t pay_col[ORC_MAX_PAYLOADS];
     int32_t fact_fk_col;
+    int32_t pay_src[ORC_MAX_PAYLOADS];
+    const struct orc_probe_s* sub;
+    int32_t nsub;
 } orc_probe;
 
 /* A value reference: src < 0 -> fact column idx; src = j -> payload idx of

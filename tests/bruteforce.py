@@ -67,25 +67,50 @@ def _nrows(table):
     return len(c.offsets) - 1 if hasattr(c, "offsets") else len(c)
 
 
+def qualifying(pr: dict, tables: dict) -> list:
+    """[(key, [payload values])] of the dimension rows a probe joins with: the
+    rows passing its filters that also find a match in each of its own
+    probes (a joined build side), found by nested loops."""
+    dim = tables[pr["dim"]]
+    subs = [qualifying(sp, tables) for sp in pr.get("probes", [])]
+    out = []
+    for d in range(_nrows(dim)):
+        if not all(pred_holds(p, dim, d) for p in pr.get("filters", [])):
+            continue
+        sub_hits = []
+        for sp, rows in zip(pr.get("probes", []), subs):
+            fk = _cell(dim[sp["fk"]], d)
+            m = [pay for key, pay in rows if key == fk]
+            if not m:
+                break
+            sub_hits.append(m[0])
+        if len(sub_hits) != len(subs):
+            continue
+        pays = []
+        for c in pr.get("payloads", []):
+            pays.append(sub_hits[c["probe"]][c["payload"]] if isinstance(c, dict) else _cell(dim[c], d))
+        out.append((_cell(dim[pr["key"]], d), pays))
+    keys = [k for k, _ in out]
+    if len(keys) != len(set(keys)):
+        raise Duplicate()
+    return out
+
+
 def evaluate(spec: dict, tables: dict) -> list:
     fact = tables[spec["fact"]]
     probes = spec.get("probes", [])
     groups = {}
+    quals = [qualifying(pr, tables) for pr in probes]  # raises Duplicate up front
     for r in range(_nrows(fact)):
         if not all(pred_holds(p, fact, r) for p in spec.get("filters", [])):
             continue
         hits = []
-        for pr in probes:
-            dim = tables[pr["dim"]]
+        for pr, rows in zip(probes, quals):
             fk = _cell(fact[pr["fk"]], r)
-            found = [d for d in range(_nrows(dim))
-                     if _cell(dim[pr["key"]], d) == fk
-                     and all(pred_holds(p, dim, d) for p in pr.get("filters", []))]
-            if len(found) > 1:
-                raise Duplicate()
+            found = [pay for key, pay in rows if key == fk]
             if not found:
                 break
-            hits.append([_cell(dim[c], found[0]) for c in pr.get("payloads", [])])
+            hits.append(found[0])
         if len(hits) != len(probes):
             continue
 
@@ -108,17 +133,6 @@ def evaluate(spec: dict, tables: dict) -> list:
                     v = _chk(_chk(t.get("mul", 1) * val(t["ref"])) + t.get("add", 0))
                 prod = _chk(prod * v)
             acc[1 + a] = _chk(acc[1 + a] + prod)
-    # A duplicate key among qualifying dimension rows is an error even if no
-    # fact row reaches it.
-    for pr in probes:
-        dim = tables[pr["dim"]]
-        seen = set()
-        for d in range(_nrows(dim)):
-            if all(pred_holds(p, dim, d) for p in pr.get("filters", [])):
-                k = _cell(dim[pr["key"]], d)
-                if k in seen:
-                    raise Duplicate()
-                seen.add(k)
     out = []
     for key in sorted(groups):
         acc = groups[key]

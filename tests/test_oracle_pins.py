@@ -70,7 +70,11 @@ def _random_instance(rng, n=300):
     d2 = {"k": rng.permutation(15).astype(np.int64),
           "x": rng.integers(0, 3, 15).astype(np.int64),
           "y": rng.integers(10, 13, 15).astype(np.int64)}
-    return {"F": fact, "D1": d1, "D2": d2}
+    # D1's rows join D3 through f3 when a query chains the build side
+    d1["f3"] = rng.integers(0, 14, 25).astype(np.int64)
+    d3 = {"k": rng.permutation(11).astype(np.int64),
+          "z": rng.integers(0, 4, 11).astype(np.int64)}
+    return {"F": fact, "D1": d1, "D2": d2, "D3": d3}
 
 
 def _random_pred(rng, cols):
@@ -94,8 +98,15 @@ def _random_query(rng):
     for j, (dim, fk) in enumerate([("D1", "fk1"), ("D2", "fk2")]):
         if rng.random() < 0.6:
             pf = [_random_pred(rng, ["x", "y"]) for _ in range(rng.integers(0, 2))]
-            probes.append({"fk": fk, "dim": dim, "key": "k", "filters": pf,
-                           "payloads": ["x", "y"][:int(rng.integers(0, 3))]})
+            pr = {"fk": fk, "dim": dim, "key": "k", "filters": pf,
+                  "payloads": ["x", "y"][:int(rng.integers(0, 3))]}
+            if dim == "D1" and rng.random() < 0.4:
+                # a joined build side: D1 rows qualify only with a D3 match
+                zf = [_random_pred(rng, ["z"]) for _ in range(rng.integers(0, 2))]
+                pr["probes"] = [{"fk": "f3", "dim": "D3", "key": "k", "filters": zf, "payloads": ["z"]}]
+                if rng.random() < 0.6:
+                    pr["payloads"] = pr["payloads"][:1] + [{"probe": 0, "payload": 0}]
+            probes.append(pr)
     refs = [{"col": "a"}, {"col": "b"}, {"col": "c"}, {"col": "p"}]
     for j, pr in enumerate(probes):
         refs += [{"probe": j, "payload": k} for k in range(len(pr["payloads"]))]
@@ -313,6 +324,12 @@ MUTANTS = [
     ("if (a[i] < b[i]) return -1;", "if (a[i] < b[i]) return 1;"),
     ("cols[pr->pay_col[k]].ival[r] : 0;", "cols[pr->pay_col[0]].ival[r] : 0;"),
     ("if (!rc && __builtin_mul_overflow(prod, v, &prod)) rc = ORC_ERR_OVERFLOW;", "if (!rc) prod *= v;"),
+    # joined build sides
+    ("hit[j] = probe_dim(&sub[j], cols[pr->sub[j].fact_fk_col].ival[r]);",
+     "hit[j] = probe_dim(&sub[j], cols[pr->sub[j].fact_fk_col].ival[r]); if (!hit[j]) hit[j] = sub[j].e;"),
+    ("e[n].pay[k] = hit[pr->pay_src[k]]->pay[pr->pay_col[k]];", "e[n].pay[k] = cols[pr->pay_col[k]].ival[r];"),
+    ("for (int32_t i = 0; i < pr->npreds && ok; ++i) ok = eval_pred(&pr->preds[i], cols, r);",
+     "for (int32_t i = 0; i < pr->npreds && ok && depth == 0; ++i) ok = eval_pred(&pr->preds[i], cols, r);"),
 ]
 
 
