@@ -242,6 +242,54 @@ def sj_query(table: str = "lo", part_attr: int = 17, supp_nation: int = 3, date_
 
 
 # ----------------------------------------------------------------------------
+# Join chain: a 3-table pipeline (customer -> orders -> lineitem)
+# ----------------------------------------------------------------------------
+def chain_tables(n_line: int = 120_000_000, seed: int = 6, n_orders: int | None = None,
+                 n_cust: int | None = None) -> dict:
+    """customer(custkey 1..C, region 0..4, segment 0..9); orders(orderkey
+    1..O, custkey uniform, priority 1..5, odate in [0, 2556)); lineitem
+    (orderkey uniform, quantity 1..50, extprice 90000..10500000 cents).  By
+    default O = n_line / 4 and C = O / 10 (the order-to-line and
+    customer-to-order ratios of a star schema's snowflake arm)."""
+    n_orders = n_orders or max(1, n_line // 4)
+    n_cust = n_cust or max(1, n_orders // 10)
+    return {
+        "customer": {"c_custkey": np.arange(1, n_cust + 1, dtype=np.int32),
+                     "c_region": uniform(seed, "c_region", n_cust, 0, 4, dtype=np.int32),
+                     "c_segment": uniform(seed, "c_segment", n_cust, 0, 9, dtype=np.int32)},
+        "orders": {"o_orderkey": np.arange(1, n_orders + 1, dtype=np.int32),
+                   "o_custkey": uniform(seed, "o_custkey", n_orders, 1, n_cust, dtype=np.int32),
+                   "o_priority": uniform(seed, "o_priority", n_orders, 1, 5, dtype=np.int32),
+                   "o_date": uniform(seed, "o_date", n_orders, 0, NDATES - 1, dtype=np.int32)},
+        "lineitem": {"l_orderkey": uniform(seed, "l_orderkey", n_line, 1, n_orders, dtype=np.int32),
+                     "l_quantity": uniform(seed, "l_quantity", n_line, 1, 50, dtype=np.int32),
+                     "l_extprice": uniform(seed, "l_extprice", n_line, 90000, 10500000, dtype=np.int64)},
+    }
+
+
+def chain_query(segment: int = 3, date_lo: int = 700, date_hi: int = 1600, qty_lt: int = 30) -> dict:
+    """Section 3.1's running example in shape: customers of one market
+    segment build table #1; orders in a date window probe it and build table
+    #2 keyed by order, carrying the customer's region and the order
+    priority; line items (quantity below a cutoff) probe table #2 and
+    aggregate count, sum(quantity) and sum(extprice * priority) by (region,
+    priority)."""
+    return {
+        "fact": "lineitem",
+        "filters": [{"col": "l_quantity", "op": "LT", "value": qty_lt}],
+        "probes": [{"fk": "l_orderkey", "dim": "orders", "key": "o_orderkey",
+                    "filters": [{"col": "o_date", "op": "BETWEEN", "lo": date_lo, "hi": date_hi}],
+                    "payloads": [{"probe": 0, "payload": 0}, "o_priority"],
+                    "probes": [{"fk": "o_custkey", "dim": "customer", "key": "c_custkey",
+                                "filters": [{"col": "c_segment", "op": "EQ", "value": segment}],
+                                "payloads": ["c_region"]}]}],
+        "group_by": [{"probe": 0, "payload": 0}, {"probe": 0, "payload": 1}],
+        "aggs": [{"op": "COUNT"}, {"op": "SUM", "terms": [{"ref": {"col": "l_quantity"}}]},
+                 {"op": "SUM", "terms": [{"ref": {"col": "l_extprice"}}, {"ref": {"probe": 0, "payload": 1}}]}],
+    }
+
+
+# ----------------------------------------------------------------------------
 # Batched mix: 64 queries over a pool of tables of log-uniform size
 # ----------------------------------------------------------------------------
 def mix_plan(seed: int = 4, nq: int = 64, min_rows: int = 1_000_000, max_rows: int = 120_000_000,
@@ -323,6 +371,6 @@ def serve_requests(seed: int, qps: float, seconds: float, table: str, stream: st
     return out
 
 
-__all__ = ["Strings", "union_table", "serve_requests", "fa_table", "fa_query", "wide_table", "wide_query", "wide_words",
+__all__ = ["Strings", "chain_tables", "chain_query", "union_table", "serve_requests", "fa_table", "fa_query", "wide_table", "wide_query", "wide_words",
            "sj_dims", "sj_fact", "sj_query", "mix_plan", "FA_ENCODINGS", "WIDE_ENCODINGS",
            "FLAG_A_VALUES", "FLAG_B_VALUES", "NDATES"]

@@ -209,16 +209,31 @@ typedef struct {
  * ------------------------------------------------------------------------ */
 enum { DPF_HASH_AUTO = 0, DPF_HASH_LDS = 1, DPF_HASH_HBM = 2 };
 typedef struct {
+    int32_t fk_col;
+    dpf_hash hash;
+} dpf_probe;
+
+typedef struct {
     int32_t ncols;
     const dpf_column* cols;     /* dimension columns (same row count)          */
     int32_t key_col;            /* unique among qualifying rows; values must fit
                                    int32 and differ from INT32_MIN              */
     int32_t npreds;
     const dpf_pred* preds;      /* integer predicates over cols                */
-    int32_t npayloads;          /* 0..2 integer payload columns                 */
-    int32_t payload_cols[2];
+    int32_t npayloads;          /* 0..2 payloads                                */
+    int32_t payload_cols[2];    /* payload k: integer column payload_cols[k], or
+                                   (payload_probe[k] >= 0) payload number
+                                   payload_cols[k] of probe payload_probe[k]     */
     int32_t placement;          /* where probes keep the table (AUTO: LDS when
                                    it fits the per-workgroup LDS budget)       */
+    /* A joined build side (paper Section 3.1, Kernel #2: a scan that probes an
+     * earlier table and builds the next): 0..2 probes of tables already built,
+     * each by an integer column fk_col of cols.  A row enters the table only
+     * if it passes preds and every probe finds its foreign key; the probed
+     * tables are read during the call only. */
+    int32_t nprobes;
+    const dpf_probe* probes;
+    int32_t payload_probe[2];   /* -1: payload k is a column of cols           */
 } dpf_hash_desc;
 
 /* Builds an open-addressing table (power-of-two capacity, load <= 1/2) in HBM
@@ -265,11 +280,6 @@ typedef struct {
     int32_t nterms; /* 1..3 for SUM and AVG */
     dpf_term terms[3];
 } dpf_agg;
-
-typedef struct {
-    int32_t fk_col;
-    dpf_hash hash;
-} dpf_probe;
 
 typedef struct {
     int32_t ncols;

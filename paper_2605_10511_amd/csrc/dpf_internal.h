@@ -184,7 +184,8 @@ struct BatchArgs {
     int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate or a probe)
 };
 
-// Hash build over a dimension table.
+// Hash build over a dimension table (optionally joined: the rows must find
+// their foreign keys in the tables of sub[], probed from device memory).
 struct HashBuildArgs {
     DevCol cols[kMaxHashCols];
     int32_t ncols;
@@ -193,7 +194,10 @@ struct HashBuildArgs {
     int64_t in_vals[kMaxIn];
     int32_t key_col;
     int32_t npay;
-    int32_t pay_col[2];
+    int32_t pay_col[2];   // column, or (pay_src >= 0) payload index of sub[pay_src]
+    int32_t pay_src[2];   // -1: a column of cols
+    int32_t nsub;
+    DevProbe sub[2];
     int32_t nmb;
     int32_t pad;
     int64_t nrows;
@@ -236,6 +240,7 @@ struct FragBuffers {
     int64_t* dec[kMaxCols];      // decoded integer columns (codes for DICT)
     int64_t* str_off[kMaxCols];  // decoded string offsets [nrows + 1]
     uint8_t* str_bytes[kMaxCols];
+    const DevCol* str_col[kMaxCols];  // the column's descriptor with its heap at str_bytes
     uint8_t* flags;              // [nrows]
     FragRow* rows[2];            // ping-pong row lists [nrows]
     int64_t* pay[2][2 * kMaxProbes];  // payload arrays aligned with the row lists

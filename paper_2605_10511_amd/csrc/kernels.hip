@@ -346,23 +346,6 @@ __device__ __forceinline__ bool bytes_eq(S s, Wp w, int from, int n) {
     return true;
 }
 
-// Does s[from, n) contain w (length nw)?
-template <class S, class Wp>
-__device__ bool contains_from(S s, uint32_t from, uint32_t n, Wp w, int nw) {
-    for (uint32_t q = from; q + (uint32_t)nw <= n; ++q)
-        if (s[q] == w[0] && bytes_eq(s + q, w, 1, nw)) return true;
-    return false;
-}
-
-// LIKE '%s1%s2%' on one string where it rests (fragmented path).
-__device__ bool contains_seq_global(const uint8_t* s, uint32_t n, CP& p) {
-    for (uint32_t a = 0; a + (uint32_t)p.n1 <= n; ++a) {
-        if (s[a] != p.s1[0] || !bytes_eq(s + a, p.s1, 1, p.n1)) continue;
-        return contains_from(s, a + p.n1, n, p.s2, p.n2);  // leftmost s1 is optimal
-    }
-    return false;
-}
-
 struct StrPattern {
     uint64_t p8, m8;  // first min(n, 8) bytes, little endian, and their mask
 };
@@ -558,13 +541,19 @@ __device__ __forceinline__ int str_mode(int n1, int n2) { return (n1 < 4 || n2 <
 
 // Returns the 4-bit match mask of the lane's rows (row 64 k + lane -> bit k)
 // for the mini block whose loads str_begin issued; clears ok on corruption.
-template <int kMode>
+// kOffsReady: the caller has written the row offsets (L.offs[0..256]) from
+// materialised string offsets, and S carries no packed lengths.
+template <int kMode, bool kOffsReady = false>
 __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvalid, StrTile& S,
                                                const StrLds& L, bool& ok) {
     if (!S.ok) { ok = false; return 0; }
     uint32_t* const offs = L.offs;
     const uint32_t s0 = (uint32_t)(S.h0 & 15u);
     const uint32_t nvec = (uint32_t)((S.h1 - (S.h0 - s0) + 15u) >> 4);
+    if (kOffsReady) {
+        reinterpret_cast<uint4*>(L.first1)[lane] = make_uint4(~0u, ~0u, ~0u, ~0u);
+        reinterpret_cast<uint4*>(L.last2)[lane] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
     // Row offsets: lane l takes rows 4l..4l+3, so one wave scan suffices.
     uint32_t len[4], lsum = 0;
     const uint64_t lmask = (uint64_t(1) << S.b) - 1;
@@ -594,6 +583,7 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
     }
     if (lane == 0) offs[256] = total;
     if ((uint64_t)total != S.h1 - S.h0) { ok = false; return 0; }
+    }
 
     const StrPattern P1 = make_pattern(p.s1, p.n1), P2 = make_pattern(p.s2, p.n2);
     // The first 4 bytes of each word (masked for kStrMasked).
@@ -1417,10 +1407,32 @@ __device__ __forceinline__ uint32_t hash_tile_mask(CHB& A, int m, int lane, int 
     if (kc.enc == ENC_DICT)
         for (int k = 0; k < 4; ++k) key[k] = dict_value(kc, key[k], ok);
     for (int j = 0; j < A.npay; ++j) {
+        if (A.pay_src[j] >= 0) continue;  // taken from a probe below
         CC& pc = A.cols[A.pay_col[j]];
         ok &= decode_dense(pc, m, lane, pay[j]);
         if (pc.enc == ENC_DICT)
             for (int k = 0; k < 4; ++k) pay[j][k] = dict_value(pc, pay[j][k], ok);
+    }
+    // A joined build side (Section 3.1, Kernel #2): each row must find its
+    // foreign key in every probed table; payloads may come from those tables.
+    for (int s = 0; s < A.nsub; ++s) {
+        if (__ballot(mask != 0) == 0) break;
+        CPR& P = A.sub[s];
+        CC& fc = A.cols[P.fk_col];
+        int64_t fk[4];
+        ok &= decode_dense(fc, m, lane, fk);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!((mask >> k) & 1u)) continue;
+            if (fc.enc == ENC_DICT) fk[k] = dict_value(fc, fk[k], ok);
+            const int slot = hash_find<false>(P.h, nullptr, fk[k]);
+            if (slot < 0) {
+                mask &= ~(1u << k);
+                continue;
+            }
+            for (int j = 0; j < A.npay; ++j)
+                if (A.pay_src[j] == s) pay[j][k] = hash_payload<false>(P.h, nullptr, A.pay_col[j], slot);
+        }
     }
     return mask;
 }
@@ -1606,16 +1618,61 @@ __global__ void frag_filter_int(const DevQuery* __restrict__ q, int pi, const in
     }
 }
 
-__global__ void frag_filter_str(const DevQuery* __restrict__ q, int pi, const int64_t* off, const uint8_t* bytes,
-                                uint8_t* flags, int first) {
+// The string atom over the materialised column: the same heap scan as the
+// fused kernel's string test (aligned-word table or byte windows), one wave
+// per 256 rows, reading the decoded offsets and the copied bytes (mcol: the
+// column's descriptor with its heap pointing at that copy); one flag per row.
+template <int kMode>
+__global__ __launch_bounds__(kBlock) void frag_filter_str(const DevQuery* __restrict__ q, const DevCol* __restrict__ mcol,
+                                                          int pi, const int64_t* __restrict__ off, uint8_t* flags,
+                                                          int first) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ __align__(16) uint32_t tab[32];
     CQ& Q = *ro(q);
     CP& P = Q.preds[pi];
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < Q.nrows;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        bool prev = first ? true : flags[r] != 0;
-        bool t = prev && contains_seq_global(bytes + off[r], (uint32_t)(off[r + 1] - off[r]), P);
-        flags[r] = (uint8_t)t;
+    CC& C = *ro(mcol);
+    if (threadIdx.x < 32) tab[threadIdx.x] = P.tab[threadIdx.x];
+    __syncthreads();
+    const int lane = lane_id();
+    const int wave = uniform_i32(threadIdx.x >> 6);
+    uint8_t* wa = smem + (size_t)wave * (260 * 4 + 2 * 256 * 4 + kRecCap * 16);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(wa);
+    const StrLds L{tab, offs, offs + 260, offs + 516, reinterpret_cast<uint4*>(offs + 772)};
+    bool ok = true;
+    for (int m = blockIdx.x * kWaves + wave; m < Q.nmb; m += gridDim.x * kWaves) {
+        const int64_t row0 = (int64_t)m * kMB;
+        const int nvalid = (int)min((int64_t)kMB, Q.nrows - row0);
+        StrTile S;
+        S.h0 = (uint64_t)ro(off)[row0];
+        S.h1 = (uint64_t)ro(off)[row0 + nvalid];
+        S.ok = S.h0 <= S.h1 && S.h1 <= C.heap_bytes && (S.h1 - S.h0) < (uint64_t(1) << 30);
+        const uint64_t a0 = S.h0 & ~uint64_t(15);
+        S.g = (cptr<uint4>)(C.heap + a0);
+        S.gp = C.heap + a0;
+        const uint32_t nvec = S.ok ? (uint32_t)((S.h1 - a0 + 15u) >> 4) : 0u;
+        if (S.ok) load_segment(S.cur, S, 0, nvec, lane);
+        // row offsets within the mini block, from the materialised offsets
+        uint4 ov;
+        const int64_t rb = row0 + 4 * lane;
+        const int64_t rend = row0 + nvalid;
+        ov.x = (uint32_t)((uint64_t)ro(off)[min(rb, rend)] - S.h0);
+        ov.y = (uint32_t)((uint64_t)ro(off)[min(rb + 1, rend)] - S.h0);
+        ov.z = (uint32_t)((uint64_t)ro(off)[min(rb + 2, rend)] - S.h0);
+        ov.w = (uint32_t)((uint64_t)ro(off)[min(rb + 3, rend)] - S.h0);
+        reinterpret_cast<uint4*>(offs)[lane] = ov;
+        if (lane == 0) offs[256] = (uint32_t)(S.h1 - S.h0);
+        const uint32_t mask = str_finish<kMode, true>(C, P, lane, nvalid, S, L, ok);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = 64 * k + lane;
+            if (i >= nvalid) continue;
+            const int64_t r = row0 + i;
+            const bool prev = first ? true : flags[r] != 0;
+            flags[r] = (uint8_t)(prev && ((mask >> k) & 1u));
+        }
+        wave_lds_sync();
     }
+    if (!ok) atomicOr(Q.status, ST_CORRUPT);
 }
 
 // flags -> row list (order not preserved; aggregation is order-free).  One
@@ -1845,10 +1902,22 @@ int run_fragmented(const DevQuery* d_q, const DevQuery& Q, const FragBuffers& fb
     // 2) one filter kernel per predicate, then compaction to a row list
     for (int p = 0; p < Q.npreds; ++p) {
         const int c = Q.preds[p].col;
-        if (Q.preds[p].kind == PK_STR)
-            hipLaunchKernelGGL(frag_filter_str, dim3(grid), dim3(256), 0, s, d_q, p, fb.str_off[c],
-                               fb.str_bytes[c], fb.flags, p == 0 ? 1 : 0);
-        else
+        if (Q.preds[p].kind == PK_STR) {
+            const DevPred& P = Q.preds[p];
+            const int mode = P.tab_rot ? kStrTable : (P.n1 < 4 || P.n2 < 4) ? kStrMasked : kStrShifted;
+            const size_t lds = (size_t)kWaves * (260 * 4 + 2 * 256 * 4 + kRecCap * 16);
+            const int64_t wgs = ((int64_t)Q.nmb + kWaves - 1) / kWaves;
+            const int sgrid = (int)(wgs < 2048 ? (wgs > 0 ? wgs : 1) : 2048);
+            if (mode == kStrTable)
+                hipLaunchKernelGGL(frag_filter_str<kStrTable>, dim3(sgrid), dim3(kBlock), lds, s, d_q, fb.str_col[c], p,
+                                   fb.str_off[c], fb.flags, p == 0 ? 1 : 0);
+            else if (mode == kStrShifted)
+                hipLaunchKernelGGL(frag_filter_str<kStrShifted>, dim3(sgrid), dim3(kBlock), lds, s, d_q, fb.str_col[c], p,
+                                   fb.str_off[c], fb.flags, p == 0 ? 1 : 0);
+            else
+                hipLaunchKernelGGL(frag_filter_str<kStrMasked>, dim3(sgrid), dim3(kBlock), lds, s, d_q, fb.str_col[c], p,
+                                   fb.str_off[c], fb.flags, p == 0 ? 1 : 0);
+        } else
             hipLaunchKernelGGL(frag_filter_int, dim3(grid), dim3(256), 0, s, d_q, p, fb.dec[c], fb.flags,
                                p == 0 ? 1 : 0);
         if (!chk()) return -1;

@@ -662,8 +662,22 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     }
     auto int_col = [&](int i) { return i >= 0 && i < desc->ncols && desc->cols[i]->host.enc != DPF_ENC_VARLEN; };
     if (!int_col(desc->key_col)) return fail(DPF_ERR_INVALID_ARG, "key column must be an integer column");
-    for (int j = 0; j < desc->npayloads; ++j)
-        if (!int_col(desc->payload_cols[j])) return fail(DPF_ERR_INVALID_ARG, "payload columns must be integer");
+    if (desc->nprobes < 0 || desc->nprobes > 2 || (desc->nprobes && !desc->probes))
+        return fail(DPF_ERR_INVALID_ARG, "0..2 probes of the build side");
+    for (int j = 0; j < desc->nprobes; ++j) {
+        const dpf_probe& pr = desc->probes[j];
+        if (!pr.hash || pr.hash->ctx != ctx) return fail(DPF_ERR_INVALID_ARG, "bad hash handle in a build-side probe");
+        if (!int_col(pr.fk_col)) return fail(DPF_ERR_INVALID_ARG, "build-side probe key must be an integer column");
+    }
+    for (int j = 0; j < desc->npayloads; ++j) {
+        const int src = desc->nprobes ? desc->payload_probe[j] : -1;
+        if (src < 0) {
+            if (!int_col(desc->payload_cols[j])) return fail(DPF_ERR_INVALID_ARG, "payload columns must be integer");
+        } else if (src >= desc->nprobes || desc->payload_cols[j] < 0 ||
+                   desc->payload_cols[j] >= desc->probes[src].hash->stats.npayloads) {
+            return fail(DPF_ERR_INVALID_ARG, "payload taken from a build-side probe: bad probe or payload index");
+        }
+    }
 
     HashBuildArgs A;
     std::memset(&A, 0, sizeof A);
@@ -686,6 +700,16 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
     A.npay = desc->npayloads;
     A.pay_col[0] = desc->npayloads > 0 ? desc->payload_cols[0] : 0;
     A.pay_col[1] = desc->npayloads > 1 ? desc->payload_cols[1] : 0;
+    A.pay_src[0] = A.pay_src[1] = -1;
+    for (int j = 0; j < desc->npayloads && desc->nprobes; ++j) A.pay_src[j] = desc->payload_probe[j];
+    A.nsub = desc->nprobes;
+    for (int j = 0; j < desc->nprobes; ++j) {
+        DevProbe& P = A.sub[j];
+        P.fk_col = desc->probes[j].fk_col;
+        P.pay_slot[0] = P.pay_slot[1] = -1;
+        P.h = desc->probes[j].hash->dev;  // read from device memory during the build
+        P.h.lds_off = P.h.filt_lds_off = P.h.bits_lds_off = -1;
+    }
     A.nrows = nrows;
     A.nmb = (int32_t)desc->cols[0]->host.nmb;
 
@@ -1291,7 +1315,12 @@ dpf_status ensure_frag(dpf_plan p) {
         if (q.cols[c].enc == ENC_VARLEN) {
             fb.str_off[c] = (int64_t*)get((n + 1) * 8);
             fb.str_bytes[c] = (uint8_t*)get(q.cols[c].heap_bytes + 64);
-            if (!fb.str_off[c] || !fb.str_bytes[c]) goto oom;
+            DevCol* dc = (DevCol*)get(sizeof(DevCol));
+            if (!fb.str_off[c] || !fb.str_bytes[c] || !dc) goto oom;
+            DevCol mc = q.cols[c];
+            mc.heap = fb.str_bytes[c];  // the string scan reads the materialised copy
+            if (hipMemcpy(dc, &mc, sizeof mc, hipMemcpyHostToDevice) != hipSuccess) goto oom;
+            fb.str_col[c] = dc;
         } else {
             fb.dec[c] = (int64_t*)get(n * 8);
             if (!fb.dec[c]) goto oom;

@@ -80,7 +80,8 @@ class dpf_pred(C.Structure):
 class dpf_hash_desc(C.Structure):
     _fields_ = [("ncols", C.c_int32), ("cols", C.c_void_p), ("key_col", C.c_int32),
                 ("npreds", C.c_int32), ("preds", C.c_void_p), ("npayloads", C.c_int32),
-                ("payload_cols", C.c_int32 * 2), ("placement", C.c_int32)]
+                ("payload_cols", C.c_int32 * 2), ("placement", C.c_int32),
+                ("nprobes", C.c_int32), ("probes", C.c_void_p), ("payload_probe", C.c_int32 * 2)]
 
 
 class dpf_hash_stats(C.Structure):
@@ -359,10 +360,13 @@ def _preds(preds: list, index: dict, keep: _Keep):
 
 
 class Hash:
-    """A dimension hash table (paper Section 3.1, Kernel #1)."""
+    """A dimension hash table (paper Section 3.1, Kernel #1; with ``probes``,
+    a joined build side as in Kernel #2: ``probes`` is a list of (foreign-key
+    column of ``cols``, Hash), and a payload {"probe": j, "payload": k} takes
+    payload k of probe j)."""
 
     def __init__(self, ctx: Context, cols: dict, key: str, filters: list, payloads: list,
-                 placement: str = "AUTO", stream=None):
+                 placement: str = "AUTO", stream=None, probes: list | None = None):
         lib = load()
         names = list(cols)
         index = {n: i for i, n in enumerate(names)}
@@ -376,8 +380,18 @@ class Hash:
         d.npreds, d.preds = len(filters), C.cast(preds, C.c_void_p)
         d.npayloads = len(payloads)
         for k, pc in enumerate(payloads):
-            d.payload_cols[k] = index[pc]
+            if isinstance(pc, dict):
+                d.payload_cols[k], d.payload_probe[k] = int(pc["payload"]), int(pc["probe"])
+            else:
+                d.payload_cols[k], d.payload_probe[k] = index[pc], -1
         d.placement = HASH_PLACEMENTS[placement]
+        probes = probes or []
+        parr = (dpf_probe * max(1, len(probes)))()
+        for j, (fk, h) in enumerate(probes):
+            parr[j].fk_col = index[fk]
+            parr[j].hash = h.h.value
+        keep.append(parr)
+        d.nprobes, d.probes = len(probes), C.cast(parr, C.c_void_p)
         h = C.c_void_p()
         _check(lib.dpf_hash_build(ctx.h, C.byref(d), _stream_handle(stream), C.byref(h)))
         self.h = h
@@ -537,15 +551,26 @@ class Database:
                              for c, v in columns.items()}
         return self.tables[name]
 
-    def build_hashes(self, spec: dict, placements: list | None = None, stream=None) -> list:
-        hs = []
-        for j, pr in enumerate(spec.get("probes", [])):
-            cols = self.tables[pr["dim"]]
-            used = [pr["key"]] + [p["col"] for p in pr.get("filters", [])] + list(pr.get("payloads", []))
+    def build_hash(self, pr: dict, placement: str = "AUTO", stream=None) -> Hash:
+        """The hash table a probe description joins with; a probe that has
+        its own "probes" (a joined build side) has those built first, used
+        during the build and released."""
+        cols = self.tables[pr["dim"]]
+        subs = [self.build_hash(sp, "AUTO", stream) for sp in pr.get("probes", [])]
+        try:
+            used = [pr["key"]] + [p["col"] for p in pr.get("filters", [])]
+            used += [c for c in pr.get("payloads", []) if not isinstance(c, dict)]
+            used += [sp["fk"] for sp in pr.get("probes", [])]
             sub = {c: cols[c] for c in dict.fromkeys(used)}
-            pl = placements[j] if placements else "AUTO"
-            hs.append(Hash(self.ctx, sub, pr["key"], pr.get("filters", []), pr.get("payloads", []), pl, stream))
-        return hs
+            return Hash(self.ctx, sub, pr["key"], pr.get("filters", []), pr.get("payloads", []), placement, stream,
+                        probes=[(sp["fk"], h) for sp, h in zip(pr.get("probes", []), subs)])
+        finally:
+            for h in subs:
+                h.release()
+
+    def build_hashes(self, spec: dict, placements: list | None = None, stream=None) -> list:
+        return [self.build_hash(pr, placements[j] if placements else "AUTO", stream)
+                for j, pr in enumerate(spec.get("probes", []))]
 
     def plan(self, spec: dict, hashes: list | None = None, placements: list | None = None) -> Plan:
         if hashes is None:

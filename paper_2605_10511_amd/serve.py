@@ -91,12 +91,8 @@ class Server:
         h = self.hashes.get(key)
         if h is None:
             t0 = time.perf_counter()
-            cols = self.db.tables[pr["dim"]]
-            used = [pr["key"]] + [p["col"] for p in pr.get("filters", [])] + list(pr.get("payloads", []))
-            sub = {c: cols[c] for c in dict.fromkeys(used)}
             s = self.streams[0]
-            h = dpf.Hash(self.ctx, sub, pr["key"], pr.get("filters", []), pr.get("payloads", []),
-                         self.placements.get(pr["dim"], "AUTO"), s)
+            h = self.db.build_hash(pr, self.placements.get(pr["dim"], "AUTO"), s)
             s.synchronize()  # later batches on other streams read it
             self.hashes[key] = h
             self.hash_bytes += h.info().device_bytes
