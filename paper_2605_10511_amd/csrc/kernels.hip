@@ -783,6 +783,13 @@ __device__ __forceinline__ bool bitmap_has(CH& h, const uint8_t* smem_shared, in
     return (w >> (d & 31)) & 1u;
 }
 
+// The same test on the bitmap in device memory (kernels without the fused
+// kernel's LDS copies).
+__device__ __forceinline__ bool bitmap_has_global(CH& h, int64_t key) {
+    const uint64_t d = (uint64_t)key - (uint64_t)h.bmin;
+    return d < h.bspan && ((ro(h.bits)[d >> 5] >> (d & 31)) & 1u);
+}
+
 // Membership of the lane's four keys (mask bit k: row 64 k + lane is live):
 // four independent bit tests when the table has a bitmap, else the hash
 // chains probed in lockstep so that their loads are in flight together.
@@ -901,9 +908,15 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, unsigned lo
                 ok = false;  // certainly absent
                 continue;
             }
-            if (P.h.bits && P.pay_slot[0] < 0 && P.pay_slot[1] < 0) {
-                ok = bitmap_has(P.h, smem_shared, fk);  // membership only
-                continue;
+            // The key-range bitmap answers membership exactly: it settles a
+            // probe that needs no payload, and keeps non-members (most rows
+            // of a selective join) away from the hash table's random reads.
+            if (P.h.bits) {
+                if (!bitmap_has(P.h, smem_shared, fk)) {
+                    ok = false;
+                    continue;
+                }
+                if (P.pay_slot[0] < 0 && P.pay_slot[1] < 0) continue;
             }
             const bool lds = P.h.lds_off >= 0;
             int slot = lds ? hash_find<true>(P.h, smem_shared, fk) : hash_find<false>(P.h, smem_shared, fk);
@@ -1425,7 +1438,8 @@ __device__ __forceinline__ uint32_t hash_tile_mask(CHB& A, int m, int lane, int 
         for (int k = 0; k < 4; ++k) {
             if (!((mask >> k) & 1u)) continue;
             if (fc.enc == ENC_DICT) fk[k] = dict_value(fc, fk[k], ok);
-            const int slot = hash_find<false>(P.h, nullptr, fk[k]);
+            const bool maybe = !P.h.bits || bitmap_has_global(P.h, fk[k]);
+            const int slot = maybe ? hash_find<false>(P.h, nullptr, fk[k]) : -1;
             if (slot < 0) {
                 mask &= ~(1u << k);
                 continue;
@@ -1740,7 +1754,8 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
             CC& fc = Q.cols[P.fk_col];
             bool okd = true;
             if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, okd);
-            slot = hash_find<false>(P.h, nullptr, fk);
+            // the same bitmap pre-test as the fused kernel's stage B
+            if (!P.h.bits || bitmap_has_global(P.h, fk)) slot = hash_find<false>(P.h, nullptr, fk);
         }
         bool keep = slot >= 0;
         uint64_t bal = __ballot(keep);
