@@ -106,11 +106,23 @@ dpf_status dpf_ctx_get_info(dpf_ctx ctx, dpf_ctx_info* out);
  *   FOR    value = base + (packed bits), width per mini block 0..64 bits;
  *   DELTA  value_i = anchor + sum over j <= i of (dmin + packed_j);
  *   DICT   codes (ranks in the sorted distinct values) packed as FOR;
- *   VARLEN string lengths packed as FOR + a contiguous byte heap.
+ *   VARLEN string lengths packed as FOR + a contiguous byte heap;
+ *   FSST   strings compressed with FSST (paper Sections 3.4.2 and 4.1): one
+ *          table of up to 255 symbols of 1..8 bytes per chunk, each string a
+ *          run of one-byte codes (code 255 escapes the literal byte after
+ *          it), code lengths packed as FOR + a contiguous code heap.
  * AUTO picks VARLEN for strings, DELTA for non-decreasing integers, else FOR.
  * ------------------------------------------------------------------------ */
 enum { DPF_TYPE_I32 = 1, DPF_TYPE_I64 = 2, DPF_TYPE_STR = 3 };
-enum { DPF_ENC_AUTO = 0, DPF_ENC_FOR = 1, DPF_ENC_DELTA = 2, DPF_ENC_DICT = 3, DPF_ENC_VARLEN = 4, DPF_ENC_PLAIN = 5 };
+enum {
+    DPF_ENC_AUTO = 0,
+    DPF_ENC_FOR = 1,
+    DPF_ENC_DELTA = 2,
+    DPF_ENC_DICT = 3,
+    DPF_ENC_VARLEN = 4,
+    DPF_ENC_PLAIN = 5,
+    DPF_ENC_FSST = 6
+};
 /* PLAIN (integers only) stores every value at full width, 32 bits for I32
  * and 64 for I64, in FOR's layout with a fixed base (INT32_MIN / INT64_MIN):
  * the uncompressed reference that separates the gain of fusion from that of
@@ -152,7 +164,7 @@ typedef struct {
                                  (+ dictionary, + string heap) */
     int64_t min, max;         /* integer columns: value range (0, 0 when empty) */
     int64_t ndict;            /* DICT: distinct values                          */
-    int64_t str_bytes;        /* VARLEN: heap bytes                             */
+    int64_t str_bytes;        /* strings: decoded bytes (the decode capacity)   */
 } dpf_column_stats;
 dpf_status dpf_column_info(dpf_column col, dpf_column_stats* out);
 
@@ -161,7 +173,7 @@ dpf_status dpf_column_info(dpf_column col, dpf_column_stats* out);
 typedef struct {
     int64_t row_start;
     int64_t nrows;
-    int64_t byte_offset, byte_length; /* of the chunk's packed data (or heap, for VARLEN) */
+    int64_t byte_offset, byte_length; /* of the chunk's packed data (or heap, for strings) */
     int64_t min, max;
 } dpf_chunk_info;
 dpf_status dpf_column_chunk(dpf_column col, int64_t chunk, dpf_chunk_info* out);

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdpf.so")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "encode.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "encode.cpp", "fsst.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are kept out of every code object.
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -21,6 +21,8 @@ constexpr int kMaxAccs = 12;      // accumulators (count + sums)
 constexpr int kMaxTerms = 3;      // factors per aggregate product
 constexpr int kMaxIn = 64;        // IN-list values per plan
 constexpr int kMaxWord = 32;      // bytes per string-predicate word
+constexpr int kFsstMaxWordBytes = 16;  // ... on an FSST column (16-bit automaton state)
+constexpr int kFsstLdsBytes = 8448;    // the FSST atom's code tables in the workgroup's shared LDS
 constexpr int kMaxBatch = 64;     // plans per fused launch
 constexpr int kMaxHashCols = 8;   // dimension columns per hash build
 constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
@@ -30,7 +32,7 @@ constexpr int kXcds = 8;             // XCDs per device; workgroup i is dispatch
 constexpr int kCounterStride = 32;   // 32-bit words between work-queue counters (128-byte lines)
 constexpr int kCounterWords = (2 * kXcds + 1) * kCounterStride;
 
-enum : int32_t { ENC_FOR = 1, ENC_DELTA = 2, ENC_DICT = 3, ENC_VARLEN = 4 };
+enum : int32_t { ENC_FOR = 1, ENC_DELTA = 2, ENC_DICT = 3, ENC_VARLEN = 4, ENC_FSST = 6 };
 
 // Device view of one encoded column (all arrays indexed by global mini block).
 struct DevCol {
@@ -38,15 +40,20 @@ struct DevCol {
     const uint32_t* woff;   // [nmb + 1] first word of each mini block's packed data
     const uint32_t* words;  // packed values, LSB first, value i at bit i * width
     const int64_t* dmin;    // DELTA: [nmb] minimum first difference
-    const uint64_t* hoff;   // VARLEN: [nmb + 1] byte offset of the mini block's strings
-    const uint8_t* heap;    // VARLEN: string bytes (padded)
+    const uint64_t* hoff;   // VARLEN, FSST: [nmb + 1] byte offset of the mini block's strings (codes)
+    const uint8_t* heap;    // VARLEN: string bytes; FSST: codes (padded)
     const int64_t* dict;    // DICT: [ndict] sorted distinct values
+    const uint64_t* doff;   // FSST: [nmb + 1] decoded byte offset of each mini block
+    const uint8_t* symtab;  // FSST: per chunk, sym[256] (uint64) then len[256] (uint8)
     int64_t nrows;
     uint64_t heap_bytes;
+    uint64_t str_bytes;     // VARLEN, FSST: decoded string bytes
     uint32_t nwords;
     int32_t nmb;
     int32_t enc;
     int32_t ndict;
+    int32_t mbpc;           // mini blocks per chunk (FSST: mini block m uses table m / mbpc)
+    int32_t pad;
 };
 
 enum : int32_t { PK_RANGE = 1, PK_NE = 2, PK_INMASK = 3, PK_INLIST = 4, PK_STR = 5, PK_FALSE = 6 };
@@ -157,6 +164,10 @@ struct DevQuery {
     int32_t agg_lds_off; // byte offset of that table
     int32_t lds_shared;  // LDS bytes of this plan's shared area (hashes + table)
     int32_t has_str;
+    // The string atom on an FSST column (index into preds, -1: none) and
+    // the byte offset of its code tables in the shared area.
+    int32_t fs_pred;
+    int32_t fs_lds_off;
     uint32_t* status;    // device status bits (ST_*)
     int64_t* host_out;   // device address of the pinned output: [status, nrec, records...]
     // Chunk pruning: null, or the ascending indices of the blocks of
@@ -180,7 +191,7 @@ struct BatchArgs {
     uint32_t* counters;   // kCounterWords: per XCD x, the claim head of item range x (line x) and
                           // its finished workgroups (line 8 + x); finished XCDs (line 16)
     int32_t lds_shared;   // max lds_shared over the batch
-    int32_t str_stage;    // per-wave string staging present
+    int32_t str_stage;    // per-wave string staging present (2: some plan has an FSST atom)
     int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate or a probe)
 };
 

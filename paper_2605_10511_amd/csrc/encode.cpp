@@ -16,6 +16,8 @@
 #include <cstring>
 #include <thread>
 
+#include "fsst.h"
+
 namespace dpf {
 namespace {
 
@@ -103,6 +105,7 @@ int64_t compressed_bytes(const HostColumn& c) {
     int64_t b = c.nmb * 8 + (c.nmb + 1) * 4 + (int64_t)c.nwords * 4;
     if (c.enc == DPF_ENC_DELTA) b += c.nmb * 8;
     if (c.enc == DPF_ENC_VARLEN) b += (c.nmb + 1) * 8 + (int64_t)c.heap_bytes;
+    if (c.enc == DPF_ENC_FSST) b += (c.nmb + 1) * 8 + (int64_t)c.heap_bytes + c.nchunks * (int64_t)kFsstTableBytes;
     if (c.enc == DPF_ENC_DICT) b += (int64_t)c.dict.size() * 8;
     return b;
 }
@@ -116,6 +119,8 @@ ColView view_of(const HostColumn& c) {
     v.hoff = c.hoff.empty() ? nullptr : c.hoff.data();
     v.heap = c.heap.empty() ? nullptr : c.heap.data();
     v.dict = c.dict.empty() ? nullptr : c.dict.data();
+    v.doff = c.doff.empty() ? nullptr : c.doff.data();
+    v.symtab = c.symtab.empty() ? nullptr : c.symtab.data();
     return v;
 }
 
@@ -140,17 +145,21 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
         return DPF_ERR_INVALID_ARG;
     }
     if (is_str && !src.str_offsets) { *err = "missing offsets"; return DPF_ERR_INVALID_ARG; }
+    const bool fsst = is_str && enc == DPF_ENC_FSST;
     if (is_str) {
         if (enc == DPF_ENC_AUTO) enc = DPF_ENC_VARLEN;
-        if (enc != DPF_ENC_VARLEN) { *err = "strings use VARLEN"; return DPF_ERR_INVALID_ARG; }
+        if (enc != DPF_ENC_VARLEN && enc != DPF_ENC_FSST) {
+            *err = "strings use VARLEN or FSST";
+            return DPF_ERR_INVALID_ARG;
+        }
         if (src.str_offsets[0] != 0) { *err = "string offsets must start at 0"; return DPF_ERR_INVALID_ARG; }
         for (int64_t i = 0; i < n; ++i)
             if (src.str_offsets[i + 1] < src.str_offsets[i]) {
                 *err = "string offsets must be non-decreasing";
                 return DPF_ERR_INVALID_ARG;
             }
-    } else if (enc == DPF_ENC_VARLEN) {
-        *err = "VARLEN is for strings";
+    } else if (enc == DPF_ENC_VARLEN || enc == DPF_ENC_FSST) {
+        *err = "VARLEN and FSST are for strings";
         return DPF_ERR_INVALID_ARG;
     }
     if (is_str && enc == DPF_ENC_PLAIN) { *err = "PLAIN is for integers"; return DPF_ERR_INVALID_ARG; }
@@ -162,7 +171,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
         for (int64_t i = 1; i < n && sorted; ++i) sorted = val(i) >= val(i - 1);
         enc = (sorted && n > 0) ? DPF_ENC_DELTA : DPF_ENC_FOR;
     }
-    if (enc < DPF_ENC_FOR || enc > DPF_ENC_PLAIN) { *err = "unknown encoding"; return DPF_ERR_INVALID_ARG; }
+    if (enc < DPF_ENC_FOR || enc > DPF_ENC_FSST) { *err = "unknown encoding"; return DPF_ERR_INVALID_ARG; }
 
     HostColumn& c = *out;
     c = HostColumn();
@@ -208,9 +217,60 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
                 codes[i] = (int32_t)(std::lower_bound(c.dict.begin(), c.dict.end(), val(i)) - c.dict.begin());
         });
     }
+    // FSST: per chunk, a symbol table from a sample of the chunk's strings
+    // (every k-th string, up to kSampleBytes, each cut to 4 KB), then every
+    // string compressed with it; clen holds the code bytes per row.
+    std::vector<uint32_t> clen;
+    if (fsst) {
+        constexpr size_t kSampleBytes = 32768;
+        constexpr size_t kSampleCut = 4096;
+        clen.resize(n);
+        c.symtab.assign(c.nchunks * kFsstTableBytes, 0);
+        std::vector<std::vector<uint8_t>> parts(c.nchunks);
+        std::vector<int> bad(c.nchunks, 0);
+        parallel_for(c.nchunks, threads, [&](int64_t a, int64_t b) {
+            for (int64_t k = a; k < b; ++k) {
+                const int64_t r0 = k * chunk_rows, r1 = std::min<int64_t>(n, r0 + chunk_rows);
+                const uint64_t bytes = (uint64_t)(src.str_offsets[r1] - src.str_offsets[r0]);
+                const int64_t stride = std::max<int64_t>(1, (int64_t)(bytes / kSampleBytes));
+                std::vector<const uint8_t*> sp;
+                std::vector<size_t> sl;
+                size_t got = 0;
+                for (int64_t r = r0; r < r1 && got < kSampleBytes; r += stride) {
+                    const size_t l = std::min<size_t>(kSampleCut, (size_t)(src.str_offsets[r + 1] - src.str_offsets[r]));
+                    sp.push_back(src.str_bytes + src.str_offsets[r]);
+                    sl.push_back(l);
+                    got += l;
+                }
+                const FsstTable t = fsst_build(sp, sl);
+                fsst_serialize(t, c.symtab.data() + k * kFsstTableBytes);
+                const FsstMatcher mt(t);
+                std::vector<uint8_t>& out = parts[k];
+                out.reserve(bytes / 2 + 64);
+                for (int64_t r = r0; r < r1; ++r) {
+                    const size_t cl = fsst_compress(mt, src.str_bytes + src.str_offsets[r],
+                                                    (size_t)(src.str_offsets[r + 1] - src.str_offsets[r]), out);
+                    if (cl > 0xFFFFFFFFu) bad[k] = 1;
+                    clen[r] = (uint32_t)cl;
+                }
+            }
+        });
+        if (std::count(bad.begin(), bad.end(), 1)) { *err = "FSST record over 4 GB"; return DPF_ERR_UNSUPPORTED; }
+        uint64_t tot = 0;
+        for (auto& pt : parts) tot += pt.size();
+        c.heap_bytes = tot;
+        c.heap.assign(tot + kHeapPad, 0);
+        uint64_t at = 0;
+        for (auto& pt : parts) {
+            if (!pt.empty()) std::memcpy(c.heap.data() + at, pt.data(), pt.size());
+            at += pt.size();
+            std::vector<uint8_t>().swap(pt);
+        }
+    }
     auto stream_at = [&](int64_t i) -> int64_t {
         if (enc == DPF_ENC_DICT) return codes[i];
         if (enc == DPF_ENC_VARLEN) return src.str_offsets[i + 1] - src.str_offsets[i];
+        if (enc == DPF_ENC_FSST) return clen[i];
         return val(i);
     };
 
@@ -273,6 +333,20 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
         for (int64_t m = 0; m < nmb; ++m) c.hoff[m] = (uint64_t)src.str_offsets[m * kMB];
         c.hoff[nmb] = c.heap_bytes;
     }
+    if (is_str) c.str_bytes = n ? (uint64_t)src.str_offsets[n] : 0;
+    if (fsst) {
+        c.hoff.resize(nmb + 1);
+        c.doff.resize(nmb + 1);
+        uint64_t h = 0;
+        for (int64_t m = 0; m < nmb; ++m) {
+            c.hoff[m] = h;
+            c.doff[m] = (uint64_t)src.str_offsets[m * kMB];
+            const int64_t e = std::min<int64_t>(n, (m + 1) * kMB);
+            for (int64_t r = m * kMB; r < e; ++r) h += clen[r];
+        }
+        c.hoff[nmb] = h;
+        c.doff[nmb] = c.str_bytes;
+    }
 
     // Chunk directory: row-id index (prefix of row counts), byte ranges and
     // zone maps (value min/max; lengths for strings).
@@ -284,7 +358,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
             ci.row_start = k * chunk_rows;
             ci.nrows = std::min<int64_t>(chunk_rows, n - ci.row_start);
             int64_t m0 = k * mbpc, m1 = std::min(nmb, m0 + mbpc);
-            if (enc == DPF_ENC_VARLEN) {
+            if (is_str) {
                 ci.byte_offset = (int64_t)c.hoff[m0];
                 ci.byte_length = (int64_t)(c.hoff[m1] - c.hoff[m0]);
             } else {
@@ -293,7 +367,7 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
             }
             int64_t mn = INT64_MAX, mx = INT64_MIN;
             for (int64_t i = ci.row_start; i < ci.row_start + ci.nrows; ++i) {
-                int64_t x = (enc == DPF_ENC_VARLEN) ? stream_at(i) : (is_str ? 0 : val(i));
+                int64_t x = is_str ? src.str_offsets[i + 1] - src.str_offsets[i] : val(i);
                 mn = std::min(mn, x);
                 mx = std::max(mx, x);
             }
@@ -315,15 +389,22 @@ dpf_status encode_column(const dpf_column_src& src, int32_t enc, int32_t chunk_r
 dpf_status decode_column(const HostColumn& c, const ColView& v, void* values, int64_t* str_offsets,
                          uint8_t* str_bytes, size_t cap, std::string* err) {
     const int64_t n = c.nrows;
-    if (c.enc == DPF_ENC_VARLEN) {
-        if (!str_offsets || (c.heap_bytes && !str_bytes)) { *err = "missing output arrays"; return DPF_ERR_INVALID_ARG; }
-        if (cap < c.heap_bytes) { *err = "string byte capacity too small"; return DPF_ERR_INVALID_ARG; }
+    const bool is_str = c.enc == DPF_ENC_VARLEN || c.enc == DPF_ENC_FSST;
+    if (is_str) {
+        if (!str_offsets || (c.str_bytes && !str_bytes)) { *err = "missing output arrays"; return DPF_ERR_INVALID_ARG; }
+        if (cap < c.str_bytes) { *err = "string byte capacity too small"; return DPF_ERR_INVALID_ARG; }
     } else if (!values && n) {
         *err = "missing output array";
         return DPF_ERR_INVALID_ARG;
     }
     int64_t off = 0;
     if (str_offsets) str_offsets[0] = 0;
+    // FSST: the lengths are code bytes; each record decodes with its chunk's
+    // table into the output at the running decoded offset.
+    const int64_t mbpc = c.chunk_rows / kMB;
+    FsstTable tab;
+    int64_t tab_chunk = -1;
+    uint64_t coff = 0;  // code offset of the current row
     for (int64_t m = 0; m < c.nmb; ++m) {
         uint32_t nw = v.woff[m + 1] - v.woff[m];
         if (nw % 8 != 0 || nw > 512) { *err = "corrupt mini-block header"; return DPF_ERR_CORRUPT; }
@@ -348,6 +429,21 @@ dpf_status decode_column(const HostColumn& c, const ColView& v, void* values, in
             if (c.enc == DPF_ENC_VARLEN) {
                 off += x;
                 str_offsets[r + 1] = off;
+            } else if (c.enc == DPF_ENC_FSST) {
+                if (m / mbpc != tab_chunk) {
+                    tab_chunk = m / mbpc;
+                    if (!fsst_deserialize(v.symtab + tab_chunk * kFsstTableBytes, &tab)) {
+                        *err = "corrupt FSST symbol table";
+                        return DPF_ERR_CORRUPT;
+                    }
+                }
+                if (i == 0) coff = v.hoff[m];
+                if (x < 0 || coff + (uint64_t)x > c.heap_bytes) { *err = "corrupt FSST lengths"; return DPF_ERR_CORRUPT; }
+                const int64_t d = fsst_decode(tab, v.heap + coff, (size_t)x, str_bytes + off, cap - (size_t)off);
+                if (d < 0) { *err = "corrupt FSST codes"; return DPF_ERR_CORRUPT; }
+                coff += (uint64_t)x;
+                off += d;
+                str_offsets[r + 1] = off;
             } else if (c.type == DPF_TYPE_I32) {
                 ((int32_t*)values)[r] = (int32_t)x;
             } else {
@@ -358,6 +454,10 @@ dpf_status decode_column(const HostColumn& c, const ColView& v, void* values, in
     if (c.enc == DPF_ENC_VARLEN) {
         if ((uint64_t)off != c.heap_bytes) { *err = "string lengths disagree with the heap"; return DPF_ERR_CORRUPT; }
         if (c.heap_bytes) std::memcpy(str_bytes, v.heap, c.heap_bytes);
+    }
+    if (c.enc == DPF_ENC_FSST && (uint64_t)off != c.str_bytes) {
+        *err = "decoded strings disagree with the column's size";
+        return DPF_ERR_CORRUPT;
     }
     return DPF_OK;
 }

@@ -22,9 +22,11 @@ struct ColView {
     const uint32_t* woff = nullptr;  // [nmb + 1]
     const uint32_t* words = nullptr; // [nwords + pad]
     const int64_t* dmin = nullptr;   // DELTA [nmb]
-    const uint64_t* hoff = nullptr;  // VARLEN [nmb + 1]
-    const uint8_t* heap = nullptr;   // VARLEN [heap_bytes + pad]
+    const uint64_t* hoff = nullptr;  // VARLEN, FSST [nmb + 1]
+    const uint8_t* heap = nullptr;   // VARLEN, FSST [heap_bytes + pad]
     const int64_t* dict = nullptr;   // DICT [ndict]
+    const uint64_t* doff = nullptr;  // FSST [nmb + 1]
+    const uint8_t* symtab = nullptr; // FSST [nchunks * kFsstTableBytes]
 };
 
 struct HostColumn {
@@ -38,9 +40,15 @@ struct HostColumn {
     std::vector<uint64_t> hoff;
     std::vector<uint8_t> heap;    // includes kHeapPad trailing zero bytes
     std::vector<int64_t> dict;
+    // FSST: the heap holds codes and the packed lengths count code bytes;
+    // doff[m] is the decoded byte offset of mini block m, symtab one
+    // serialized symbol table per chunk.
+    std::vector<uint64_t> doff;
+    std::vector<uint8_t> symtab;
     std::vector<ChunkInfo> chunks;
     uint64_t nwords = 0;          // packed words, excluding padding
-    uint64_t heap_bytes = 0;      // string bytes, excluding padding
+    uint64_t heap_bytes = 0;      // string (FSST: code) bytes, excluding padding
+    uint64_t str_bytes = 0;       // decoded string bytes
 };
 
 constexpr int kWordPad = 16;
@@ -48,7 +56,8 @@ constexpr int kHeapPad = 64;
 
 // Bytes a full scan of the column reads: packed words and mini-block headers
 // (base, word offset; DELTA minimum difference; VARLEN heap offset and heap;
-// DICT dictionary).
+// FSST heap offset, code heap and one symbol table per chunk; DICT
+// dictionary).
 int64_t compressed_bytes(const HostColumn& c);
 
 // Encodes src.  enc is a DPF_ENC_* value (AUTO resolved here).  Returns a

@@ -716,6 +716,242 @@ __device__ __forceinline__ uint32_t str_pred(CC& c, CP& p, int m, int lane, int 
 }
 
 // ---------------------------------------------------------------------------
+// FSST strings (Sections 3.4.2 and 4.1): each chunk carries a table of up to
+// 255 symbols of 1..8 bytes; a record is a run of one-byte codes, code 255
+// escaping the literal byte after it.  The string test runs on the decoded
+// symbols without writing any decoded byte: the two words are matched with
+// the bit-parallel shift-and automaton (state bit i: the word's first i + 1
+// bytes end at the current position), and because its step is
+//     D' = ((D << 1) | 1) & B[x]
+// (B[x] bit i: byte i of the word is x), feeding a whole symbol of L bytes
+// collapses to one step
+//     D' = ((D << L) & M) | C
+// with M, C fixed by the symbol.  Whether the word completes somewhere
+// inside the symbol is, likewise, (D & F) != 0 or f.  The workgroup derives
+// M, C, F, f for every code of the chunk's table once (two sets: the first
+// word, then the second word searched after the first one's leftmost end)
+// and each lane then walks its records code by code, one LDS read a code.
+// Codes whose symbol completes a word, and escapes, take a byte-at-a-time
+// path that also performs the switch to the second word.
+//
+// Workgroup LDS of an FSST atom (DevQuery::fs_lds_off):
+//   B[2][256]  uint32  byte masks of the two words (built with the plan)
+//   E[2][256]  uint2   per code: {M | F << 16 | f << 31, C | L << 16};
+//                      escape and unused codes: f = 1, L = 0
+//   sym[256]   uint64  the chunk's symbols, len[256] uint8 their lengths
+// Words have at most kFsstMaxWordBytes (16) bytes, so M, C fit 16 bits and
+// F 15.
+// ---------------------------------------------------------------------------
+constexpr size_t kFsstB = 0, kFsstE = 2048, kFsstSym = 6144, kFsstLen = 8192;
+static_assert(kFsstLen + 256 == kFsstLdsBytes && kFsstMaxWordBytes <= 16, "FSST LDS layout");
+
+__device__ __forceinline__ uint32_t fsst_word_mask(cptr<uint8_t> w, int n, uint32_t x) {
+    uint32_t b = 0;
+    for (int i = 0; i < n; ++i) b |= (uint32_t)(w[i] == x) << i;
+    return b;
+}
+
+// The byte masks of the plan's FSST atom (with the plan's other LDS state).
+__device__ void fsst_load_masks(CQ& Q, uint8_t* smem_shared) {
+    if (Q.fs_pred < 0) return;
+    CP& P = Q.preds[Q.fs_pred];
+    uint32_t* B = reinterpret_cast<uint32_t*>(smem_shared + Q.fs_lds_off + kFsstB);
+    for (uint32_t x = threadIdx.x; x < 256; x += blockDim.x) {
+        B[x] = fsst_word_mask(P.s1, P.n1, x);
+        B[256 + x] = fsst_word_mask(P.s2, P.n2, x);
+    }
+}
+
+// Code tables of chunk k of the FSST column (the masks must be in place).
+__device__ void fsst_load_chunk(CQ& Q, uint8_t* smem_shared, int k) {
+    CP& P = Q.preds[Q.fs_pred];
+    CC& c = Q.cols[P.col];
+    uint8_t* T = smem_shared + Q.fs_lds_off;
+    const uint32_t* B = reinterpret_cast<const uint32_t*>(T + kFsstB);
+    uint2* E = reinterpret_cast<uint2*>(T + kFsstE);
+    uint64_t* sym = reinterpret_cast<uint64_t*>(T + kFsstSym);
+    uint8_t* len = T + kFsstLen;
+    cptr<uint8_t> tab = ro(c.symtab) + (size_t)k * (256 * 8 + 256);
+    for (uint32_t code = threadIdx.x; code < 256; code += blockDim.x) {
+        const uint64_t sv = ((cptr<uint64_t>)tab)[code];
+        const uint32_t L = code < 255 ? min((uint32_t)tab[256 * 8 + code], 8u) : 0u;
+        sym[code] = sv;
+        len[code] = (uint8_t)L;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            const int n = ph ? P.n2 : P.n1;
+            if (L == 0) {
+                E[ph * 256 + code] = make_uint2(0x80000000u, 0u);
+                continue;
+            }
+            uint32_t M = (1u << n) - 1u, C = 0, F = 0, f = 0;
+            for (uint32_t j = 1; j <= L; ++j) {
+                const uint32_t b = B[ph * 256 + (uint32_t)((sv >> (8 * (j - 1))) & 0xFF)];
+                M = (M << 1) & b;
+                C = ((C << 1) | 1u) & b;
+                if ((int)j <= n - 1 && ((M >> (n - 1)) & 1u)) F |= 1u << (n - 1 - (int)j);
+                f |= (C >> (n - 1)) & 1u;
+            }
+            E[ph * 256 + code] = make_uint2(M | (F << 16) | (f << 31), C | (L << 16));
+        }
+    }
+}
+
+// One byte through the automaton of phase ph (0: first word, 1: second word,
+// 2: matched).
+__device__ __forceinline__ void fsst_step(const uint32_t* B, int n1, int n2, uint32_t x, uint32_t& D,
+                                          uint32_t& ph) {
+    if (ph >= 2) return;
+    const int n = ph ? n2 : n1;
+    D = ((D << 1) | 1u) & B[ph * 256 + x];
+    if ((D >> (n - 1)) & 1u) {
+        D = 0;
+        ++ph;
+    }
+}
+
+// The string atom on FSST mini block m: returns the mask of rows that
+// contain s1 and, after its leftmost end, s2 (row 64 k + lane -> bit k).
+// Lane l takes rows 4 l .. 4 l + 3, whose codes are contiguous in the heap.
+// A lane's run of codes through a 32-byte register window x:y at heap
+// offset A (16-byte aligned, A <= pos < A + 16).  The heap is padded, so
+// the window's loads stay inside it while pos is at most the heap's end.
+struct CodeReader {
+    cptr<uint4> hv;
+    uint64_t pos, A;
+    uint4 x, y;
+    __device__ __forceinline__ void init(const uint8_t* heap, uint64_t p) {
+        hv = (cptr<uint4>)heap;
+        pos = p;
+        A = p & ~uint64_t(15);
+        x = ld4(hv, (uint32_t)(A >> 4));
+        y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+    }
+    // the next 4 code bytes, first in the low byte
+    // (two-way selects: a four-way pick by o >> 2 compiles to a stack copy
+    // of the window and an indexed load)
+    __device__ __forceinline__ uint32_t peek4() const {
+        const uint32_t o = (uint32_t)(pos - A);
+        const bool half = (o & 8u) != 0;
+        const uint32_t a0 = half ? x.z : x.x, a1 = half ? x.w : x.y, b0 = half ? y.x : x.z;
+        const uint32_t lo = __builtin_amdgcn_alignbyte(a1, a0, o & 3u);
+        const uint32_t hi = __builtin_amdgcn_alignbyte(b0, a1, o & 3u);
+        return (o & 4u) ? hi : lo;
+    }
+    __device__ __forceinline__ void advance(uint32_t n) {
+        pos += n;
+        if (pos - A < 16) return;
+        if (pos - A < 32) {
+            x = y;
+            A += 16;
+            y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+        } else {
+            A = pos & ~uint64_t(15);
+            x = ld4(hv, (uint32_t)(A >> 4));
+            y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+        }
+    }
+};
+
+// Code lengths of rows 4 lane .. 4 lane + 3 of FSST mini block m (rows from
+// nvalid on: 0) and the mini block's code range; false on a corrupt header.
+__device__ __forceinline__ bool fsst_lengths(CC& c, int m, int lane, int nvalid, uint32_t rl[4], uint32_t& lsum,
+                                             uint32_t& incl, uint64_t& h0) {
+    const MbHdr h = mb_hdr(c, m);
+    h0 = ro(c.hoff)[m];
+    const uint64_t h1 = ro(c.hoff)[m + 1];
+    if (!(h.ok && h.b <= 32 && h0 <= h1 && h1 <= c.heap_bytes && (h1 - h0) < (uint64_t(1) << 30))) return false;
+    lsum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = 4 * lane + j;
+        rl[j] = r < nvalid ? (uint32_t)h.base + (uint32_t)(h.b ? bits_at(h.w, (uint32_t)r * (uint32_t)h.b, h.b) : 0) : 0u;
+        lsum += rl[j];
+    }
+    incl = wave_incl_scan_u32(lsum);
+    return (uint64_t)__builtin_amdgcn_readlane(incl, 63) == h1 - h0;
+}
+
+// fl: 256 bytes of the wave's LDS for the transposition.
+__device__ __forceinline__ uint32_t fsst_pred(CQ& Q, CC& c, CP& p, int m, int lane, int nvalid, uint8_t* fl,
+                                              const uint8_t* smem_shared, bool& ok) {
+    const uint8_t* T = smem_shared + Q.fs_lds_off;
+    const uint32_t* B = reinterpret_cast<const uint32_t*>(T + kFsstB);
+    const uint2* E = reinterpret_cast<const uint2*>(T + kFsstE);
+    const uint64_t* sym = reinterpret_cast<const uint64_t*>(T + kFsstSym);
+    const uint8_t* len = T + kFsstLen;
+    uint32_t rl[4], lsum, incl;
+    uint64_t h0;
+    if (!fsst_lengths(c, m, lane, nvalid, rl, lsum, incl, h0)) { ok = false; return 0; }
+    CodeReader R;
+    R.init(c.heap, h0 + (incl - lsum));
+    uint32_t res = 0;
+    bool esc = false;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+        // (a select, not rl[r]: a dynamic index would put rl in scratch)
+        uint32_t rem = r == 0 ? rl[0] : r == 1 ? rl[1] : r == 2 ? rl[2] : rl[3];
+        uint32_t D = 0, ph = 0;
+        while (rem) {
+            const uint32_t q = R.peek4();
+            const uint32_t nq = min(rem, 4u);
+            const uint2* Et = E + ph * 256;
+            uint2 e[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) e[j] = Et[(q >> (8 * j)) & 0xFFu];
+            const uint32_t D0 = D;
+            uint32_t hit = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool act = (uint32_t)j < nq;
+                hit |= act ? (((D << 16) | 0x80000000u) & e[j].x) : 0u;
+                const uint32_t nd = (((D << (e[j].y >> 16)) & e[j].x) | e[j].y) & 0xFFFFu;
+                D = act ? nd : D;
+            }
+            if (hit | (uint32_t)esc) {
+                // byte at a time: escapes, and a word completing in a symbol
+                D = D0;
+                for (uint32_t j = 0; j < nq && ph < 2; ++j) {
+                    const uint32_t cd = (q >> (8 * j)) & 0xFFu;
+                    if (esc) {
+                        fsst_step(B, p.n1, p.n2, cd, D, ph);
+                        esc = false;
+                    } else if (cd == 255u) {
+                        esc = true;
+                    } else {
+                        const uint32_t L = len[cd];
+                        if (L == 0) ok = false;  // a code the table does not define
+                        const uint64_t sv = sym[cd];
+                        for (uint32_t b = 0; b < L && ph < 2; ++b)
+                            fsst_step(B, p.n1, p.n2, (uint32_t)(sv >> (8 * b)) & 0xFFu, D, ph);
+                    }
+                }
+            }
+            // matched: the rest of the record is skipped
+            const uint32_t adv = ph >= 2 ? rem : nq;
+            rem -= adv;
+            R.advance(adv);
+        }
+        if (ph >= 2) {
+            esc = false;
+        } else if (esc) {
+            ok = false;  // an escape without its byte
+            esc = false;
+        }
+        res |= (uint32_t)(ph >= 2) << r;
+    }
+    // rows 4 lane + j -> rows 64 k + lane, through LDS
+    reinterpret_cast<uint32_t*>(fl)[lane] =
+        (res & 1u) | ((res >> 1) & 1u) << 8 | ((res >> 2) & 1u) << 16 | ((res >> 3) & 1u) << 24;
+    wave_lds_sync();
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mask |= (uint32_t)(fl[64 * k + lane] != 0) << k;
+    wave_lds_sync();
+    return mask;
+}
+
+// ---------------------------------------------------------------------------
 // Value slots carried by a surviving row.  Fact-column loads occupy slots
 // 0..nloads-1, probe payloads the slots after them.  In the fused kernel the
 // slots live in the wave's LDS area (one int64 column per lane, so runtime
@@ -1029,9 +1265,9 @@ __device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, uns
 // 64 k + lane -> bit k).  kEager: the plan's one string atom comes last and
 // its loads are issued before the integer atoms run, so both wait for memory
 // once, together.
-template <bool kEager, bool kStr>
-__device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m, int lane, int nvalid,
-                                                bool& ok_hdr) {
+template <bool kEager, int kStr>
+__device__ __forceinline__ uint32_t filter_tile(CQ& Q, const uint8_t* smem_shared, const WaveArea& W, int m, int lane,
+                                                int nvalid, bool& ok_hdr) {
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) mask |= (uint32_t)(64 * k + lane < nvalid) << k;
@@ -1048,6 +1284,9 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
             if (!kStr) {
                 ok_hdr = false;  // unreachable: the launch picks the string instantiation
                 return 0;
+            } else if (kStr == 2 && Q.cols[P.col].enc == ENC_FSST) {
+                mask &= fsst_pred(Q, Q.cols[P.col], P, m, lane, nvalid, reinterpret_cast<uint8_t*>(W.offs),
+                                  smem_shared, ok_hdr);
             } else {
                 // (the table is loaded for the plan's last atom only)
                 if (str_mode(P.n1, P.n2) == kStrShifted)
@@ -1079,7 +1318,7 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const WaveArea& W, int m,
     return mask;
 }
 
-template <bool kStr>
+template <int kStr>
 __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                              int m, int lane, int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
@@ -1097,9 +1336,11 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsign
         return;
     }
     if (npreds == 0) return;  // probes without predicates: semi_tiles handles those plans
-    const uint32_t mask = Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR
-                              ? (kStr ? filter_tile<true, kStr>(Q, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
-                              : filter_tile<false, kStr>(Q, W, m, lane, nvalid, ok_hdr);
+    // (an FSST atom is never the eager one: its plan has fs_pred >= 0)
+    const uint32_t mask =
+        Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR && Q.fs_pred < 0
+            ? (kStr ? filter_tile<true, kStr>(Q, smem_shared, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
+            : filter_tile<false, kStr>(Q, smem_shared, W, m, lane, nvalid, ok_hdr);
     queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
@@ -1295,8 +1536,10 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 // ---------------------------------------------------------------------------
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
-template <int NW, bool kStr>
-__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr ? 6 : 4, 8))) void fused_kernel(BatchArgs a) {
+// kStr: 0 no string atom in the batch, 1 string atoms on VARLEN columns, 2
+// also an FSST atom.
+template <int NW, int kStr>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr == 2 ? 5 : kStr ? 6 : 4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // Static LDS: its address is known when the kernel is compiled, so the
     // string scan's table reads take it as an immediate offset.
@@ -1317,6 +1560,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
     unsigned long long sink = 0;  // old values of this thread's device-scope atomics
     bool direct = false;          // some plan aggregated straight into global memory
     int cur = -1;
+    int fs_chunk = -1;  // chunk whose FSST code tables are in LDS
     bool ok_hdr = true;
     int npend = 0;
     for (;;) {
@@ -1349,6 +1593,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             }
             __syncthreads();
             load_lds_state(Q, shared_area, str_tab);
+            if (kStr == 2) fsst_load_masks(Q, shared_area);
+            fs_chunk = -1;
             __syncthreads();
             cur = qi;
             direct |= Q.agg_lds == 0;
@@ -1367,11 +1613,29 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             mb0 = t * a.mb_per_item;
             mb1 = min(mb0 + a.mb_per_item, Q.nmb);
         }
-        if (Q.npreds == 0 && Q.nprobes > 0)
+        if (Q.npreds == 0 && Q.nprobes > 0) {
             semi_tiles<NW>(Q, shared_area, gagg, W, mb0 + wave, mb1, lane, npend, ok_hdr);
-        else
+        } else if (kStr == 2 && Q.fs_pred >= 0) {
+            // FSST: the item's mini blocks chunk by chunk, each chunk's code
+            // tables built once by the workgroup
+            const int mbpc = max(Q.cols[Q.preds[Q.fs_pred].col].mbpc, 1);
+            for (int s0 = mb0; s0 < mb1;) {
+                const int k = s0 / mbpc;
+                const int s1 = min(mb1, (k + 1) * mbpc);
+                if (k != fs_chunk) {
+                    __syncthreads();
+                    fsst_load_chunk(Q, shared_area, k);
+                    __syncthreads();
+                    fs_chunk = k;
+                }
+                for (int m = s0 + wave; m < s1; m += NW)
+                    process_tile<kStr>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
+                s0 = s1;
+            }
+        } else {
             for (int m = mb0 + wave; m < mb1; m += NW)
                 process_tile<kStr>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
+        }
         if (kStr && npend) flush_pending(Q, shared_area, gagg, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
@@ -1620,6 +1884,131 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
     if (!ok) atomicOr(Q.status, ST_CORRUPT);
 }
 
+// FSST record decode (Section 4.1): one wave per mini block, lane l on rows
+// 4 l .. 4 l + 3.  Pass 1 walks the codes for the decoded record lengths and
+// a wave prefix sum gives every row's output offset; pass 2 decodes the
+// records in parallel into an LDS staging window, copied out with
+// coalesced stores (a mini block larger than the window takes several
+// windows).  Each wave takes a contiguous run of mini blocks and keeps the
+// symbol table of the current chunk in its LDS.
+constexpr int kFsstStage = 8192;
+constexpr size_t kFsstDecodeWaveBytes = 256 * 8 + 256 + kFsstStage;
+
+__global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __restrict__ q, int c, int64_t* off,
+                                                           uint8_t* bytes) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    CQ& Q = *ro(q);
+    CC& C = Q.cols[c];
+    const int lane = lane_id();
+    const int wave = uniform_i32(threadIdx.x >> 6);
+    uint8_t* wa = smem + (size_t)wave * kFsstDecodeWaveBytes;
+    uint64_t* sym = reinterpret_cast<uint64_t*>(wa);
+    uint8_t* len = wa + 256 * 8;
+    uint8_t* stage = wa + 256 * 8 + 256;
+    const int nw = gridDim.x * kWaves;
+    const int gw = blockIdx.x * kWaves + wave;
+    const int per = (Q.nmb + nw - 1) / nw;
+    const int m0 = gw * per, m1 = min(Q.nmb, m0 + per);
+    const int mbpc = max(C.mbpc, 1);
+    int chunk = -1;
+    bool ok = true;
+    for (int m = m0; m < m1; ++m) {
+        const int nvalid = (int)min((int64_t)kMB, Q.nrows - (int64_t)m * kMB);
+        if (m / mbpc != chunk) {
+            chunk = m / mbpc;
+            cptr<uint8_t> tab = ro(C.symtab) + (size_t)chunk * (256 * 8 + 256);
+            wave_lds_sync();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = 64 * j + lane;
+                sym[e] = ((cptr<uint64_t>)tab)[e];
+                len[e] = e < 255 ? (uint8_t)min((uint32_t)tab[256 * 8 + e], 8u) : (uint8_t)0;
+            }
+            wave_lds_sync();
+        }
+        uint32_t rl[4], lsum, incl;
+        uint64_t h0;
+        if (!fsst_lengths(C, m, lane, nvalid, rl, lsum, incl, h0)) { ok = false; continue; }
+        const uint64_t d0 = ro(C.doff)[m], d1 = ro(C.doff)[m + 1];
+        if (!(d0 <= d1 && d1 <= C.str_bytes)) { ok = false; continue; }
+        // pass 1: decoded lengths
+        uint32_t dl[4] = {0, 0, 0, 0}, dsum = 0;
+        CodeReader R;
+        R.init(C.heap, h0 + (incl - lsum));
+        bool esc = false;
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r) {
+            uint32_t rem = r == 0 ? rl[0] : r == 1 ? rl[1] : r == 2 ? rl[2] : rl[3], n = 0;
+            while (rem) {
+                const uint32_t qd = R.peek4(), nq = min(rem, 4u);
+                for (uint32_t j = 0; j < nq; ++j) {
+                    const uint32_t cd = (qd >> (8 * j)) & 0xFFu;
+                    if (esc) { n += 1; esc = false; }
+                    else if (cd == 255u) esc = true;
+                    else if (len[cd] == 0) ok = false;
+                    else n += len[cd];
+                }
+                rem -= nq;
+                R.advance(nq);
+            }
+            if (esc) { ok = false; esc = false; }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dl[j] = j == r ? n : dl[j];
+            dsum += n;
+        }
+        const uint32_t dincl = wave_incl_scan_u32(dsum);
+        const uint32_t dtotal = __builtin_amdgcn_readlane(dincl, 63);
+        if ((uint64_t)dtotal != d1 - d0) { ok = false; continue; }
+        uint32_t start = dincl - dsum;
+        {
+            uint32_t o = start;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * lane + j;
+                if (r < nvalid) off[(int64_t)m * kMB + r] = (int64_t)(d0 + o);
+                o += dl[j];
+            }
+        }
+        // pass 2: decode window by window
+        for (uint32_t w0 = 0; w0 < dtotal; w0 += kFsstStage) {
+            const uint32_t wn = min((uint32_t)kFsstStage, dtotal - w0);
+            if (start < w0 + wn && start + dsum > w0) {
+                R.init(C.heap, h0 + (incl - lsum));
+                uint32_t d = start;  // decoded position of the next byte
+                uint32_t rem = lsum;
+                while (rem && d < w0 + wn) {
+                    const uint32_t qd = R.peek4(), nq = min(rem, 4u);
+                    for (uint32_t j = 0; j < nq; ++j) {
+                        const uint32_t cd = (qd >> (8 * j)) & 0xFFu;
+                        if (esc) {
+                            if (d - w0 < wn) stage[d - w0] = (uint8_t)cd;
+                            d += 1;
+                            esc = false;
+                        } else if (cd == 255u) {
+                            esc = true;
+                        } else {
+                            const uint32_t L = len[cd];
+                            const uint64_t sv = sym[cd];
+                            for (uint32_t b = 0; b < L; ++b)
+                                if (d + b - w0 < wn) stage[d + b - w0] = (uint8_t)(sv >> (8 * b));
+                            d += L;
+                        }
+                    }
+                    rem -= nq;
+                    R.advance(nq);
+                }
+                esc = false;
+            }
+            wave_lds_sync();
+            uint8_t* dst = bytes + d0 + w0;
+            for (uint32_t i = lane; i < wn; i += kWave) dst[i] = stage[i];
+            wave_lds_sync();
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[Q.nrows] = (int64_t)C.str_bytes;
+    if (!ok) atomicOr(Q.status, ST_CORRUPT);
+}
+
 __global__ void frag_filter_int(const DevQuery* __restrict__ q, int pi, const int64_t* vals, uint8_t* flags,
                                 int first) {
     CQ& Q = *ro(q);
@@ -1829,10 +2218,11 @@ __global__ void frag_reset_counts(unsigned long long* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-// Two instantiations per workgroup size: only batches with a string atom
+// Three instantiations per workgroup size: only batches with a string atom
 // carry the string stage's code and registers (its segment buffers and
-// record queue); the other instantiation is smaller and spills nothing.
-template <int NW, bool kStr>
+// record queue), and only those with an FSST atom the FSST walk; the plain
+// instantiation is smaller and spills nothing.
+template <int NW, int kStr>
 hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
@@ -1850,12 +2240,15 @@ size_t fused_wave_area_bytes(bool str, bool pend) { return wave_area_bytes(str, 
 
 hipError_t launch_fused(const BatchArgs& a, int waves, int grid, size_t lds_bytes, hipStream_t s) {
     switch (waves) {
-        case 4: return a.str_stage ? launch_fused_nw<4, true>(a, grid, lds_bytes, s)
-                                   : launch_fused_nw<4, false>(a, grid, lds_bytes, s);
-        case 8: return a.str_stage ? launch_fused_nw<8, true>(a, grid, lds_bytes, s)
-                                   : launch_fused_nw<8, false>(a, grid, lds_bytes, s);
-        case 16: return a.str_stage ? launch_fused_nw<16, true>(a, grid, lds_bytes, s)
-                                    : launch_fused_nw<16, false>(a, grid, lds_bytes, s);
+        case 4: return a.str_stage == 2 ? launch_fused_nw<4, 2>(a, grid, lds_bytes, s)
+                       : a.str_stage ? launch_fused_nw<4, 1>(a, grid, lds_bytes, s)
+                                     : launch_fused_nw<4, 0>(a, grid, lds_bytes, s);
+        case 8: return a.str_stage == 2 ? launch_fused_nw<8, 2>(a, grid, lds_bytes, s)
+                       : a.str_stage ? launch_fused_nw<8, 1>(a, grid, lds_bytes, s)
+                                     : launch_fused_nw<8, 0>(a, grid, lds_bytes, s);
+        case 16: return a.str_stage == 2 ? launch_fused_nw<16, 2>(a, grid, lds_bytes, s)
+                        : a.str_stage ? launch_fused_nw<16, 1>(a, grid, lds_bytes, s)
+                                      : launch_fused_nw<16, 0>(a, grid, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1909,6 +2302,9 @@ int run_fragmented(const DevQuery* d_q, const DevQuery& Q, const FragBuffers& fb
         if (Q.cols[c].enc == ENC_VARLEN) {
             hipLaunchKernelGGL(frag_decode_str, dim3(grid), dim3(kBlock), 0, s, d_q, c, fb.str_off[c],
                                fb.str_bytes[c]);
+        } else if (Q.cols[c].enc == ENC_FSST) {
+            hipLaunchKernelGGL(frag_decode_fsst, dim3(grid), dim3(kBlock), kWaves * kFsstDecodeWaveBytes, s, d_q, c,
+                               fb.str_off[c], fb.str_bytes[c]);
         } else {
             hipLaunchKernelGGL(frag_decode_int, dim3(grid), dim3(kBlock), 0, s, d_q, c, fb.dec[c]);
         }

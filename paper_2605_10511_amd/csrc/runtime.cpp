@@ -299,7 +299,7 @@ namespace {
 // Lays the encoded arrays out in one blob (256-byte aligned sections);
 // returns offsets.
 struct BlobLayout {
-    size_t base, woff, words, dmin, hoff, heap, dict, total;
+    size_t base, woff, words, dmin, hoff, heap, dict, doff, symtab, total;
 };
 
 BlobLayout layout_of(const HostColumn& h) {
@@ -313,6 +313,8 @@ BlobLayout layout_of(const HostColumn& h) {
     L.hoff = take(h.hoff.size() * 8);
     L.heap = take(h.heap.size());
     L.dict = take(h.dict.size() * 8);
+    L.doff = take(h.doff.size() * 8);
+    L.symtab = take(h.symtab.size());
     L.total = std::max<size_t>(o, 256);
     return L;
 }
@@ -326,6 +328,8 @@ void fill_blob(const HostColumn& h, const BlobLayout& L, uint8_t* dst) {
     put(L.hoff, h.hoff.data(), h.hoff.size() * 8);
     put(L.heap, h.heap.data(), h.heap.size());
     put(L.dict, h.dict.data(), h.dict.size() * 8);
+    put(L.doff, h.doff.data(), h.doff.size() * 8);
+    put(L.symtab, h.symtab.data(), h.symtab.size());
 }
 
 DevCol dev_view(const HostColumn& h, const BlobLayout& L, const uint8_t* base) {
@@ -337,8 +341,12 @@ DevCol dev_view(const HostColumn& h, const BlobLayout& L, const uint8_t* base) {
     d.hoff = h.hoff.empty() ? nullptr : reinterpret_cast<const uint64_t*>(base + L.hoff);
     d.heap = h.heap.empty() ? nullptr : base + L.heap;
     d.dict = h.dict.empty() ? nullptr : reinterpret_cast<const int64_t*>(base + L.dict);
+    d.doff = h.doff.empty() ? nullptr : reinterpret_cast<const uint64_t*>(base + L.doff);
+    d.symtab = h.symtab.empty() ? nullptr : base + L.symtab;
+    d.mbpc = h.chunk_rows / 256;
     d.nrows = h.nrows;
     d.heap_bytes = h.heap_bytes;
+    d.str_bytes = h.str_bytes;
     d.nwords = (uint32_t)h.nwords;
     d.nmb = (int32_t)h.nmb;
     d.enc = h.enc == DPF_ENC_PLAIN ? ENC_FOR : h.enc;  // PLAIN is FOR at full width
@@ -355,6 +363,8 @@ ColView host_view(const HostColumn& h, const BlobLayout& L, const uint8_t* base)
     v.hoff = h.hoff.empty() ? nullptr : reinterpret_cast<const uint64_t*>(base + L.hoff);
     v.heap = h.heap.empty() ? nullptr : base + L.heap;
     v.dict = h.dict.empty() ? nullptr : reinterpret_cast<const int64_t*>(base + L.dict);
+    v.doff = h.doff.empty() ? nullptr : reinterpret_cast<const uint64_t*>(base + L.doff);
+    v.symtab = h.symtab.empty() ? nullptr : base + L.symtab;
     return v;
 }
 }  // namespace
@@ -418,6 +428,8 @@ extern "C" dpf_status dpf_column_encode(dpf_ctx ctx, const dpf_column_src* src, 
                 std::vector<int64_t>().swap(h.dmin);
                 std::vector<uint64_t>().swap(h.hoff);
                 std::vector<uint8_t>().swap(h.heap);
+                std::vector<uint64_t>().swap(h.doff);
+                std::vector<uint8_t>().swap(h.symtab);
                 // the dictionary stays on the host for result decoding
                 c->view.dict = h.dict.empty() ? nullptr : h.dict.data();
             }
@@ -444,7 +456,7 @@ extern "C" dpf_status dpf_column_info(dpf_column col, dpf_column_stats* out) {
     s.min = h.minv;
     s.max = h.maxv;
     s.ndict = (int64_t)h.dict.size();
-    s.str_bytes = (int64_t)h.heap_bytes;
+    s.str_bytes = (int64_t)h.str_bytes;
     *out = s;
     return DPF_OK;
 }
@@ -545,6 +557,8 @@ void build_str_table(DevPred& d) {
     }
 }
 
+inline bool is_string_enc(int32_t enc) { return enc == DPF_ENC_VARLEN || enc == DPF_ENC_FSST; }
+
 // Translates p on column c into d.  *drop = the atom is always true.
 dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<int64_t>& in_vals, DevPred& d,
                           bool* drop) {
@@ -553,18 +567,21 @@ dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<in
     d.col = p.col;
     const bool dict = c.enc == DPF_ENC_DICT;
     if (p.op == DPF_OP_STR_CONTAINS_SEQ) {
-        if (c.enc != DPF_ENC_VARLEN) return fail(DPF_ERR_INVALID_ARG, "string predicate on a non-string column");
+        if (!is_string_enc(c.enc)) return fail(DPF_ERR_INVALID_ARG, "string predicate on a non-string column");
         if (p.n1 < 1 || p.n2 < 1 || p.n1 > kMaxWord || p.n2 > kMaxWord || !p.s1 || !p.s2)
             return fail(DPF_ERR_UNSUPPORTED, "string predicate words must have 1..32 bytes");
+        // the FSST test keeps a word's automaton state in 16 bits
+        if (c.enc == DPF_ENC_FSST && (p.n1 > kFsstMaxWordBytes || p.n2 > kFsstMaxWordBytes))
+            return fail(DPF_ERR_UNSUPPORTED, "string predicate words on an FSST column must have 1..16 bytes");
         d.kind = PK_STR;
         d.n1 = p.n1;
         d.n2 = p.n2;
         std::memcpy(d.s1, p.s1, p.n1);
         std::memcpy(d.s2, p.s2, p.n2);
-        build_str_table(d);
+        if (c.enc == DPF_ENC_VARLEN) build_str_table(d);
         return DPF_OK;
     }
-    if (c.enc == DPF_ENC_VARLEN) return fail(DPF_ERR_UNSUPPORTED, "integer predicate on a string column");
+    if (is_string_enc(c.enc)) return fail(DPF_ERR_UNSUPPORTED, "integer predicate on a string column");
     if (p.op == DPF_OP_NE) {
         if (dict) {
             auto it = std::lower_bound(c.dict.begin(), c.dict.end(), p.a);
@@ -660,7 +677,7 @@ extern "C" dpf_status dpf_hash_build(dpf_ctx ctx, const dpf_hash_desc* desc, dpf
         if (!c || c->host.nrows != nrows) return fail(DPF_ERR_INVALID_ARG, "dimension columns differ in length");
         if (c->placement == DPF_PLACE_HOST) return fail(DPF_ERR_INVALID_ARG, "dimension column not on the device");
     }
-    auto int_col = [&](int i) { return i >= 0 && i < desc->ncols && desc->cols[i]->host.enc != DPF_ENC_VARLEN; };
+    auto int_col = [&](int i) { return i >= 0 && i < desc->ncols && !is_string_enc(desc->cols[i]->host.enc); };
     if (!int_col(desc->key_col)) return fail(DPF_ERR_INVALID_ARG, "key column must be an integer column");
     if (desc->nprobes < 0 || desc->nprobes > 2 || (desc->nprobes && !desc->probes))
         return fail(DPF_ERR_INVALID_ARG, "0..2 probes of the build side");
@@ -876,6 +893,12 @@ void assign_lds(dpf_plan p, int32_t budget) {
     if (budget < 0) budget = kDefaultLdsHash;
     std::vector<int> order;
     int32_t off = 0;
+    // an FSST atom's code tables come first: they are not optional
+    q.fs_lds_off = -1;
+    if (q.fs_pred >= 0) {
+        q.fs_lds_off = off;
+        off += kFsstLdsBytes;
+    }
     // A probe that needs no payload only asks membership: its key-range
     // bitmap (when it has one) is the structure placed in LDS.
     for (int j = 0; j < q.nprobes; ++j) {
@@ -1055,6 +1078,13 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     q.nint_preds = q.npreds;
     for (auto& d : strs) q.preds[q.npreds++] = d;
     q.has_str = !strs.empty();
+    // the fused kernel keeps the code tables of one FSST atom per plan
+    q.fs_pred = -1;
+    for (int i = q.nint_preds; i < q.npreds; ++i) {
+        if (desc->cols[q.preds[i].col]->host.enc != DPF_ENC_FSST) continue;
+        if (q.fs_pred >= 0) return bail(fail(DPF_ERR_UNSUPPORTED, "a plan takes at most one FSST string predicate"));
+        q.fs_pred = i;
+    }
     std::copy(in_vals.begin(), in_vals.end(), q.in_vals);
 
     // probes
@@ -1062,7 +1092,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     for (int j = 0; j < desc->nprobes; ++j) {
         const dpf_probe& pr = desc->probes[j];
         if (!pr.hash || pr.hash->ctx != ctx) return bail(fail(DPF_ERR_INVALID_ARG, "bad hash handle"));
-        if (pr.fk_col < 0 || pr.fk_col >= desc->ncols || desc->cols[pr.fk_col]->host.enc == DPF_ENC_VARLEN)
+        if (pr.fk_col < 0 || pr.fk_col >= desc->ncols || is_string_enc(desc->cols[pr.fk_col]->host.enc))
             return bail(fail(DPF_ERR_INVALID_ARG, "probe key must be an integer fact column"));
         q.probes[j].fk_col = pr.fk_col;
         q.probes[j].pay_slot[0] = q.probes[j].pay_slot[1] = -1;
@@ -1078,7 +1108,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         if (r.kind == DPF_REF_COL) {
             if (r.idx < 0 || r.idx >= desc->ncols) return fail(DPF_ERR_INVALID_ARG, "reference column out of range");
             const HostColumn& c = desc->cols[r.idx]->host;
-            if (c.enc == DPF_ENC_VARLEN) return fail(DPF_ERR_UNSUPPORTED, "string columns cannot be keys or terms");
+            if (is_string_enc(c.enc)) return fail(DPF_ERR_UNSUPPORTED, "string columns cannot be keys or terms");
             bool dict_code = c.enc == DPF_ENC_DICT && !as_value;
             k = {0, r.idx, dict_code ? 0 : 1};
             if (dict_code) { *lo = 0; *hi = (int64_t)c.dict.size() - 1; *dict = desc->cols[r.idx]->view.dict; }
@@ -1312,13 +1342,15 @@ dpf_status ensure_frag(dpf_plan p) {
     for (int l = 0; l < q.nloads; ++l) needed[q.loads[l].col] = true;
     for (int c = 0; c < q.ncols; ++c) {
         if (!needed[c]) continue;
-        if (q.cols[c].enc == ENC_VARLEN) {
+        if (q.cols[c].enc == ENC_VARLEN || q.cols[c].enc == ENC_FSST) {
             fb.str_off[c] = (int64_t*)get((n + 1) * 8);
-            fb.str_bytes[c] = (uint8_t*)get(q.cols[c].heap_bytes + 64);
+            fb.str_bytes[c] = (uint8_t*)get(q.cols[c].str_bytes + 64);
             DevCol* dc = (DevCol*)get(sizeof(DevCol));
             if (!fb.str_off[c] || !fb.str_bytes[c] || !dc) goto oom;
             DevCol mc = q.cols[c];
             mc.heap = fb.str_bytes[c];  // the string scan reads the materialised copy
+            mc.heap_bytes = mc.str_bytes;
+            mc.enc = ENC_VARLEN;
             if (hipMemcpy(dc, &mc, sizeof mc, hipMemcpyHostToDevice) != hipSuccess) goto oom;
             fb.str_col[c] = dc;
         } else {
@@ -1424,7 +1456,7 @@ dpf_status launch_fused_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans, con
     std::memset(&a, 0, sizeof a);
     a.nq = n;
     a.counters = ws.counters;
-    bool str = false, pend = false;
+    bool str = false, pend = false, fsst = false;
     int32_t shared = 0;
     int64_t total_mb = 0;
     for (int i = 0; i < n; ++i) {
@@ -1433,12 +1465,13 @@ dpf_status launch_fused_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans, con
         a.agg[i] = ws.agg[i];
         a.status[i] = ws.status[i];
         str |= q.has_str != 0;
+        fsst |= q.fs_pred >= 0;
         pend |= q.npreds > 0 || q.nprobes > 0;
         shared = std::max(shared, q.lds_shared);
         total_mb += q.live ? std::min<int64_t>(q.nmb, (int64_t)q.nlive * q.prune_mb) : q.nmb;
     }
     a.lds_shared = (int32_t)align_up((size_t)shared, 16);
-    a.str_stage = str;
+    a.str_stage = fsst ? 2 : str ? 1 : 0;
     a.pend_stage = pend;
     auto lds_for = [&](int w) { return kLdsHeadBytes + (size_t)a.lds_shared + (size_t)w * fused_wave_area_bytes(str, pend); };
     // Waves per workgroup: large LDS-resident dimension tables are shared

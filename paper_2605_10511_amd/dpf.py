@@ -26,14 +26,14 @@ DPF_ERR_INVALID_ARG, DPF_ERR_OOM, DPF_ERR_HIP, DPF_ERR_UNSUPPORTED = -1, -2, -3,
 DPF_ERR_OVERFLOW, DPF_ERR_CAPACITY, DPF_ERR_DUPLICATE_KEY, DPF_ERR_CORRUPT, DPF_ERR_NOT_READY = -5, -6, -7, -8, -9
 DPF_MEM_HBM, DPF_MEM_HOST_MAPPED = 0, 1
 DPF_TYPE_I32, DPF_TYPE_I64, DPF_TYPE_STR = 1, 2, 3
-DPF_ENC_AUTO, DPF_ENC_FOR, DPF_ENC_DELTA, DPF_ENC_DICT, DPF_ENC_VARLEN, DPF_ENC_PLAIN = 0, 1, 2, 3, 4, 5
+DPF_ENC_AUTO, DPF_ENC_FOR, DPF_ENC_DELTA, DPF_ENC_DICT, DPF_ENC_VARLEN, DPF_ENC_PLAIN, DPF_ENC_FSST = 0, 1, 2, 3, 4, 5, 6
 DPF_PLACE_HBM, DPF_PLACE_HOST_MAPPED, DPF_PLACE_HOST = 0, 1, 2
 DPF_OP = {"LT": 1, "LE": 2, "GT": 3, "GE": 4, "EQ": 5, "NE": 6, "BETWEEN": 7, "IN": 8, "STR_CONTAINS_SEQ": 9}
 DPF_HASH_AUTO, DPF_HASH_LDS, DPF_HASH_HBM = 0, 1, 2
 DPF_REF_COL, DPF_REF_PAYLOAD = 0, 1
 DPF_AGG = {"COUNT": 0, "SUM": 1, "AVG": 2}
 DPF_MODE_FUSED, DPF_MODE_FRAGMENTED = 0, 1
-ENCODINGS = {"AUTO": 0, "FOR": 1, "DELTA": 2, "DICT": 3, "VARLEN": 4, "PLAIN": 5}
+ENCODINGS = {"AUTO": 0, "FOR": 1, "DELTA": 2, "DICT": 3, "VARLEN": 4, "PLAIN": 5, "FSST": 6}
 PLACEMENTS = {"HBM": 0, "HOST_MAPPED": 1, "HOST": 2}
 HASH_PLACEMENTS = {"AUTO": 0, "LDS": 1, "HBM": 2}
 
