@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="wide",
-                    choices=["wide", "fa", "sj", "mix", "serve", "prune", "ablation", "sweep", "chain"])
+                    choices=["wide", "fa", "sj", "mix", "serve", "prune", "ablation", "sweep", "chain", "fsst"])
     ap.add_argument("--no-tune", action="store_true", help="mix: skip the knob sweep")
     ap.add_argument("--qps", default="50,100,200,500", help="serve: arrival rates")
     ap.add_argument("--seconds", type=float, default=30.0, help="serve: run time per rate")
@@ -246,6 +246,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "chain":
         return bench_chain(args)
+    if args.workload == "fsst":
+        return bench_fsst(args)
 
     import torch
     import oracle
@@ -668,6 +670,78 @@ def bench_chain(args):
         "cpu_baseline": cpu, "parity_vs_oracle": parity}), flush=True)
 
 
+def bench_fsst(args):
+    """The wide string query with its comment column as VARLEN (offsets and
+    bytes) and as FSST (Sections 3.4.2, 4.1), resting in HBM and in pinned
+    host memory read over the host link: compressed bytes, fused and
+    fragmented time, and the FSST result against the oracle."""
+    import torch
+    from paper_2605_10511_amd import dpf
+
+    tables, encs, spec, nrows, desc, _ = workload("wide", args.scale)
+    ctx = dpf.Context(0)
+    stream = torch.cuda.current_stream()
+    runs, results = {}, {}
+    for enc in ("VARLEN", "FSST"):
+        e = dict(encs["fact"])
+        e["comment"] = enc
+        for place in ("HBM", "HOST_MAPPED"):
+            db = dpf.Database(ctx)
+            t0 = time.time()
+            db.add_table("fact", tables["fact"], e, placement=place)
+            enc_s = time.time() - t0
+            plan = db.plan(spec)
+            cols = db.tables["fact"]
+            nbytes = sum(cols[c].info().compressed_bytes for c in referenced_columns(spec))
+            key = f"{enc.lower()}_{place.lower()}"
+            runs[key] = {"encode_s": enc_s, "bytes": nbytes, "comment_bytes": cols["comment"].info().compressed_bytes}
+            modes = (("FUSED", args.steps, args.warmup), ("FRAGMENTED", max(2, args.frag_steps), 1))
+            for mode, steps, warm in modes if place == "HBM" else modes[:1]:
+                for _ in range(warm):
+                    dpf.execute(ctx, [plan], mode=mode).release()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rs = [dpf.execute(ctx, [plan], mode=mode) for _ in range(steps if place == "HBM" else max(3, steps // 4))]
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / len(rs)
+                results[f"{key}_{mode.lower()}"] = rs[-1].get(0)
+                for r in rs:
+                    r.release()
+                runs[key][f"{mode.lower()}_ms"] = ms
+                runs[key][f"{mode.lower()}_gbps"] = nbytes / (ms * 1e-3) / 1e9
+                log(f"[fsst] {enc} {place} {mode}: {ms:.3f} ms, {nbytes / 1e9:.3f} GB referenced "
+                    f"({nbytes / nrows:.2f} B/row; comment {runs[key]['comment_bytes'] / nrows:.2f} B/row)")
+            plan.release()
+            del db
+    ref = results["varlen_hbm_fused"]
+    same = all(np.array_equal(ref, r) for r in results.values())
+    cpu, parity = None, None
+    if not args.no_oracle:
+        want, cpu = oracle_baseline(spec, tables, nrows, f"the {nrows:,}-row wide string query")
+        parity = bool(np.array_equal(want, results["fsst_hbm_fused"]))
+        log(f"[fsst] FSST result {'==' if parity else '!='} oracle")
+    f = runs["fsst_hbm"]
+    ms = f["fused_ms"]
+    print(json.dumps({
+        "metric": METRIC, "value": nrows / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"wide string query, comment column FSST vs VARLEN ({nrows:,} rows), "
+                               f"HBM and host-mapped", "rows": nrows},
+        "roofline": {"bound": "hbm", "achieved": f["fused_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": f["fused_gbps"] / HBM_PEAK_GBPS, "traffic": None, "kernel": "fused_kernel",
+                     "kernel_ms": ms, "algorithmic_bytes": f["bytes"]},
+        "runs": runs, "all_results_equal": same,
+        "fsst_vs_varlen": {"bytes": runs["varlen_hbm"]["bytes"] / f["bytes"],
+                           "fused_hbm_speedup": runs["varlen_hbm"]["fused_ms"] / ms,
+                           "fused_host_speedup": runs["varlen_host_mapped"]["fused_ms"] / runs["fsst_host_mapped"]["fused_ms"],
+                           "fragmented_hbm_speedup": runs["varlen_hbm"]["fragmented_ms"] / f["fragmented_ms"]},
+        "cpu_baseline": cpu, "parity_vs_oracle": parity}), flush=True)
+
+
 def bench_mix(args):
     """Config 4: 64 queries in one fused launch vs 64 solo launches vs the
     fragmented path; knob tuner; batch == solo == oracle for every query."""
@@ -679,12 +753,39 @@ def bench_mix(args):
 
     M, tables, encs = mix_tables(args.scale)
     ctx = dpf.Context(0)
-    db = dpf.Database(ctx)
-    t0 = time.time()
-    for name, cols in tables.items():
-        db.add_table(name, cols, encs.get(name), placement="HBM")
-    log(f"[mix] {len(tables)} tables encoded + uploaded in {time.time() - t0:.1f} s")
     specs = [q[2] for q in M["queries"]]
+
+    def encode(chunk_rows):
+        d = dpf.Database(ctx)
+        for name, cols in tables.items():
+            d.add_table(name, cols, encs.get(name), chunk_rows=chunk_rows, placement="HBM")
+        return d
+
+    best, tuned, chunk_rows = {}, None, 65536
+    if not args.no_tune:
+        # the encode-time chunk size with the launch knobs, each encoding
+        # tuned over the launch grid
+        def make_plans(rows):
+            d = encode(rows)
+            ps = [d.plan(sp) for sp in specs]
+
+            def release():
+                for p in ps:
+                    p.release()
+                    for h in p.hashes:
+                        h.release()
+                for t in d.tables.values():
+                    for c in t.values():
+                        c.release()
+                d.tables.clear()
+            return ps, release
+        tuned = tune.tune_chunks(ctx, make_plans, refresh=True, log=log)
+        best = dict(tuned["best"])
+        chunk_rows = best.pop("chunk_rows")
+        log(f"[mix] tuner best chunk_rows {chunk_rows}, {best}: {tuned['ms']:.3f} ms")
+    t0 = time.time()
+    db = encode(chunk_rows)
+    log(f"[mix] {len(tables)} tables encoded ({chunk_rows}-row chunks) + uploaded in {time.time() - t0:.1f} s")
     plans = [db.plan(sp) for sp in specs]
     torch.cuda.synchronize()
     rows = [db.tables[sp["fact"]][referenced_columns(sp)[0]].info().nrows for sp in specs]
@@ -704,13 +805,6 @@ def bench_mix(args):
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps, (time.perf_counter() - w0) * 1e3 / reps, out[-1]
-
-    best = {}
-    tuned = None
-    if not args.no_tune:
-        tuned = tune.tune(ctx, plans, refresh=True, log=log)
-        best = dict(tuned["best"])
-        log(f"[mix] tuner best {best}: {tuned['ms']:.3f} ms")
 
     def batch():
         return dpf.execute(ctx, plans, **best)
@@ -800,7 +894,7 @@ def bench_mix(args):
         "data": "synthetic",
         "config": {"workload": "batched mix: 64 queries (filter-aggregate / star-join, 50/50) over a pool of "
                                "4 + 4 fact tables of log-uniform size in [1M, 120M] rows, one fused launch",
-                   "query_rows": tot_rows, "compressed_bytes": tot_bytes, "knobs": best},
+                   "query_rows": tot_rows, "compressed_bytes": tot_bytes, "knobs": dict(best, chunk_rows=chunk_rows)},
         "compressed_gbps": tot_bytes / (bwall * 1e-3) / 1e9,
         "launches_per_batch": blaunch,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

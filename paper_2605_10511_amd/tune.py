@@ -1,4 +1,4 @@
-"""Launch-knob autotuner for fused executions.
+"""Autotuner for fused executions.
 
 A fused launch has three knobs that trade load balance against per-item
 overhead and LDS residency (paper Section 3.2 leaves the thread-block and
@@ -14,6 +14,10 @@ tables in shared memory):
 median of ``reps`` runs after one warm-up), skips points the library rejects
 (an LDS budget that does not fit, for instance), and caches the table and
 the winner in a JSON file keyed by the device and the shapes of the plans.
+
+``tune_chunks`` adds the encode-time axis, the chunk size (the paper's page
+size, which Section 5.3 varies): the caller re-encodes its tables at each
+size in ``CHUNK_ROWS`` and each encoding is tuned over the launch grid.
 """
 from __future__ import annotations
 
@@ -29,6 +33,7 @@ GRID = {
     "wg_per_cu": [1, 2, 4, 6],
     "lds_hash_bytes": [0, 32768, 65536, 131072],
 }
+CHUNK_ROWS = [16384, 32768, 65536, 131072]
 MAX_LDS_PER_CU = 160 * 1024
 
 
@@ -75,13 +80,14 @@ def time_point(ctx, plans: list, knobs: dict, reps: int = 3, stream=None) -> flo
 
 
 def tune(ctx, plans: list, grid: dict | None = None, reps: int = 3, cache: str | None = None,
-         refresh: bool = False, stream=None, log=None) -> dict:
+         refresh: bool = False, stream=None, log=None, tag: str = "") -> dict:
     """Return {"best": knobs, "ms": t, "table": [...], "key": ...}, from the
-    cache when it holds this key (unless ``refresh``)."""
+    cache when it holds this key (unless ``refresh``); ``tag`` extends the
+    key (the chunk size, for ``tune_chunks``)."""
     import torch
     grid = grid or GRID
     path = cache or default_cache_path()
-    key = signature(plans, torch.cuda.get_device_name(ctx.device))
+    key = signature(plans, torch.cuda.get_device_name(ctx.device)) + (f"|{tag}" if tag else "")
     db = {}
     if os.path.exists(path):
         try:
@@ -118,3 +124,25 @@ def tune(ctx, plans: list, grid: dict | None = None, reps: int = 3, cache: str |
     except OSError:
         pass  # an unwritable cache only costs a re-tune
     return entry
+
+
+def tune_chunks(ctx, make_plans, chunk_rows: list | None = None, grid: dict | None = None, reps: int = 3,
+                cache: str | None = None, refresh: bool = False, stream=None, log=None) -> dict:
+    """Tune the chunk size with the launch knobs.  ``make_plans(rows)``
+    encodes the caller's tables with chunks of ``rows`` rows and returns
+    (plans, release), release() freeing them.  Returns {"best": {"chunk_rows":
+    ..., knobs...}, "ms": t, "per_chunk": [{"chunk_rows", "best", "ms",
+    "seconds"}]}."""
+    per = []
+    for rows in chunk_rows or CHUNK_ROWS:
+        t0 = time.time()
+        plans, release = make_plans(rows)
+        try:
+            e = tune(ctx, plans, grid, reps, cache, refresh, stream, log, tag=f"chunk_rows={rows}")
+        finally:
+            release()
+        per.append({"chunk_rows": rows, "best": e["best"], "ms": e["ms"], "seconds": time.time() - t0})
+        if log:
+            log(f"[tune] chunk_rows {rows}: best {e['best']} -> {e['ms']:.3f} ms")
+    win = min(per, key=lambda p: p["ms"])
+    return {"best": {"chunk_rows": win["chunk_rows"], **win["best"]}, "ms": win["ms"], "per_chunk": per}

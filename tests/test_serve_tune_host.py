@@ -64,6 +64,30 @@ def test_tune_grid_respects_lds():
     assert {"rows_per_item": 131072, "wg_per_cu": 4, "lds_hash_bytes": 65536} not in pts
 
 
+def test_tune_chunks_picks_the_fastest_encoding(monkeypatch):
+    """The chunk-size axis: every size in CHUNK_ROWS is encoded, tuned under
+    its own cache tag and released; the winner carries its chunk size and
+    launch knobs."""
+    made, released, tags = [], [], []
+    fake_ms = {16384: 3.0, 32768: 2.0, 65536: 2.5, 131072: 4.0}
+
+    def fake_tune(ctx, plans, grid, reps, cache, refresh, stream, log, tag=""):
+        tags.append(tag)
+        rows = plans[0]
+        return {"best": {"rows_per_item": rows * 2, "wg_per_cu": 2, "lds_hash_bytes": 0}, "ms": fake_ms[rows]}
+
+    def make(rows):
+        made.append(rows)
+        return [rows], lambda: released.append(rows)
+
+    monkeypatch.setattr(tune, "tune", fake_tune)
+    out = tune.tune_chunks(None, make)
+    assert made == tune.CHUNK_ROWS == released
+    assert tags == [f"chunk_rows={r}" for r in tune.CHUNK_ROWS]
+    assert out["best"] == {"chunk_rows": 32768, "rows_per_item": 65536, "wg_per_cu": 2, "lds_hash_bytes": 0}
+    assert out["ms"] == 2.0 and len(out["per_chunk"]) == 4
+
+
 def test_union_table_has_both_templates():
     t = W.union_table(5000, seed=5)
     for c in ("date", "quantity", "price", "discount", "flagA", "flagB",
