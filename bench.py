@@ -834,14 +834,16 @@ def bench_mix(args):
         with torch.cuda.graph(graph, stream=gstream):
             gres = dpf.execute(ctx, plans, stream=gstream, **best)
     torch.cuda.synchronize()
-    graph.replay()
-    torch.cuda.synchronize()
-    g0 = torch.cuda.Event(enable_timing=True)
-    g1 = torch.cuda.Event(enable_timing=True)
-    g0.record(gstream)
-    for _ in range(args.steps):
+    # replay() launches on the current stream: the events go on that stream
+    with torch.cuda.stream(gstream):
         graph.replay()
-    g1.record(gstream)
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(gstream)
+        for _ in range(args.steps):
+            graph.replay()
+        g1.record(gstream)
     torch.cuda.synchronize()
     gms = g0.elapsed_time(g1) / args.steps
     graph_eq = all(np.array_equal(gres.get(i), got_b[i]) for i in range(len(plans)))

@@ -21,8 +21,6 @@ constexpr int kMaxAccs = 12;      // accumulators (count + sums)
 constexpr int kMaxTerms = 3;      // factors per aggregate product
 constexpr int kMaxIn = 64;        // IN-list values per plan
 constexpr int kMaxWord = 32;      // bytes per string-predicate word
-constexpr int kFsstMaxWordBytes = 16;  // ... on an FSST column (16-bit automaton state)
-constexpr int kFsstLdsBytes = 8448;    // the FSST atom's code tables in the workgroup's shared LDS
 constexpr int kMaxBatch = 64;     // plans per fused launch
 constexpr int kMaxHashCols = 8;   // dimension columns per hash build
 constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
@@ -164,10 +162,15 @@ struct DevQuery {
     int32_t agg_lds_off; // byte offset of that table
     int32_t lds_shared;  // LDS bytes of this plan's shared area (hashes + table)
     int32_t has_str;
-    // The string atom on an FSST column (index into preds, -1: none) and
-    // the byte offset of its code tables in the shared area.
+    // The string atom on an FSST column (index into preds, -1: none): its
+    // byte automaton (fs_states rows of 256 next states, device memory) and
+    // the byte offset of its code table ((2 fs_states + 1) rows of 256) in
+    // the shared area.
     int32_t fs_pred;
     int32_t fs_lds_off;
+    int32_t fs_states;
+    int32_t fs_pad;
+    const uint8_t* fs_dfa;
     uint32_t* status;    // device status bits (ST_*)
     int64_t* host_out;   // device address of the pinned output: [status, nrec, records...]
     // Chunk pruning: null, or the ascending indices of the blocks of

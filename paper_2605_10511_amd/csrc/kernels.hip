@@ -718,120 +718,80 @@ __device__ __forceinline__ uint32_t str_pred(CC& c, CP& p, int m, int lane, int 
 // ---------------------------------------------------------------------------
 // FSST strings (Sections 3.4.2 and 4.1): each chunk carries a table of up to
 // 255 symbols of 1..8 bytes; a record is a run of one-byte codes, code 255
-// escaping the literal byte after it.  The string test runs on the decoded
-// symbols without writing any decoded byte: the two words are matched with
-// the bit-parallel shift-and automaton (state bit i: the word's first i + 1
-// bytes end at the current position), and because its step is
-//     D' = ((D << 1) | 1) & B[x]
-// (B[x] bit i: byte i of the word is x), feeding a whole symbol of L bytes
-// collapses to one step
-//     D' = ((D << L) & M) | C
-// with M, C fixed by the symbol.  Whether the word completes somewhere
-// inside the symbol is, likewise, (D & F) != 0 or f.  The workgroup derives
-// M, C, F, f for every code of the chunk's table once (two sets: the first
-// word, then the second word searched after the first one's leftmost end)
-// and each lane then walks its records code by code, one LDS read a code.
-// Codes whose symbol completes a word, and escapes, take a byte-at-a-time
-// path that also performs the switch to the second word.
-//
-// Workgroup LDS of an FSST atom (DevQuery::fs_lds_off):
-//   B[2][256]  uint32  byte masks of the two words (built with the plan)
-//   E[2][256]  uint2   per code: {M | F << 16 | f << 31, C | L << 16};
-//                      escape and unused codes: f = 1, L = 0
-//   sym[256]   uint64  the chunk's symbols, len[256] uint8 their lengths
-// Words have at most kFsstMaxWordBytes (16) bytes, so M, C fit 16 bits and
-// F 15.
+// escaping the literal byte after it.  The string test never writes a
+// decoded byte: LIKE '%s1%s2%' is a byte automaton D with S = |s1| + |s2|
+// + 1 states (the two words' Knuth-Morris-Pratt automata in sequence, built
+// with the plan), and the workgroup lifts it to the chunk's codes,
+//     T[q][c] = the state D reaches from q over the bytes of symbol c,
+// so that a lane steps one code per LDS byte read.  The escape joins the
+// same table: T[q][255] = S + q, whose row is D itself (the literal byte's
+// step), and codes the chunk does not define lead to a sink row 2S.  T has
+// 2S + 1 rows of 256 bytes (DevQuery::fs_lds_off); rows S .. 2S are loaded
+// with the plan, rows 0 .. S-1 for every chunk.
 // ---------------------------------------------------------------------------
-constexpr size_t kFsstB = 0, kFsstE = 2048, kFsstSym = 6144, kFsstLen = 8192;
-static_assert(kFsstLen + 256 == kFsstLdsBytes && kFsstMaxWordBytes <= 16, "FSST LDS layout");
 
-__device__ __forceinline__ uint32_t fsst_word_mask(cptr<uint8_t> w, int n, uint32_t x) {
-    uint32_t b = 0;
-    for (int i = 0; i < n; ++i) b |= (uint32_t)(w[i] == x) << i;
-    return b;
-}
-
-// The byte masks of the plan's FSST atom (with the plan's other LDS state).
-__device__ void fsst_load_masks(CQ& Q, uint8_t* smem_shared) {
+// Rows S .. 2S of the plan's code table: the byte automaton and the sink.
+__device__ void fsst_load_dfa(CQ& Q, uint8_t* smem_shared) {
     if (Q.fs_pred < 0) return;
-    CP& P = Q.preds[Q.fs_pred];
-    uint32_t* B = reinterpret_cast<uint32_t*>(smem_shared + Q.fs_lds_off + kFsstB);
-    for (uint32_t x = threadIdx.x; x < 256; x += blockDim.x) {
-        B[x] = fsst_word_mask(P.s1, P.n1, x);
-        B[256 + x] = fsst_word_mask(P.s2, P.n2, x);
-    }
+    const uint32_t S = (uint32_t)Q.fs_states;
+    uint8_t* T = smem_shared + Q.fs_lds_off;
+    cptr<uint4> src = (cptr<uint4>)Q.fs_dfa;
+    uint4* dst = reinterpret_cast<uint4*>(T + S * 256);
+    for (uint32_t e = threadIdx.x; e < S * 16; e += blockDim.x) dst[e] = ld4(src, e);
+    for (uint32_t e = threadIdx.x; e < 256; e += blockDim.x) T[2 * S * 256 + e] = (uint8_t)(2 * S);
 }
 
-// Code tables of chunk k of the FSST column (the masks must be in place).
+// Rows 0 .. S-1 of the code table for chunk k (rows S .. 2S in place).
 __device__ void fsst_load_chunk(CQ& Q, uint8_t* smem_shared, int k) {
     CP& P = Q.preds[Q.fs_pred];
     CC& c = Q.cols[P.col];
+    const uint32_t S = (uint32_t)Q.fs_states;
     uint8_t* T = smem_shared + Q.fs_lds_off;
-    const uint32_t* B = reinterpret_cast<const uint32_t*>(T + kFsstB);
-    uint2* E = reinterpret_cast<uint2*>(T + kFsstE);
-    uint64_t* sym = reinterpret_cast<uint64_t*>(T + kFsstSym);
-    uint8_t* len = T + kFsstLen;
+    const uint8_t* D = T + S * 256;
     cptr<uint8_t> tab = ro(c.symtab) + (size_t)k * (256 * 8 + 256);
     for (uint32_t code = threadIdx.x; code < 256; code += blockDim.x) {
         const uint64_t sv = ((cptr<uint64_t>)tab)[code];
-        const uint32_t L = code < 255 ? min((uint32_t)tab[256 * 8 + code], 8u) : 0u;
-        sym[code] = sv;
-        len[code] = (uint8_t)L;
-#pragma unroll
-        for (int ph = 0; ph < 2; ++ph) {
-            const int n = ph ? P.n2 : P.n1;
-            if (L == 0) {
-                E[ph * 256 + code] = make_uint2(0x80000000u, 0u);
-                continue;
+        const uint32_t L = code < 255 ? (uint32_t)tab[256 * 8 + code] : 0u;
+        for (uint32_t q = 0; q < S; ++q) {
+            uint32_t st;
+            if (code == 255) {
+                st = S + q;
+            } else if (L == 0 || L > 8) {
+                st = 2 * S;
+            } else {
+                st = q;
+                for (uint32_t b = 0; b < L; ++b) st = D[st * 256 + (uint32_t)((sv >> (8 * b)) & 0xFF)];
             }
-            uint32_t M = (1u << n) - 1u, C = 0, F = 0, f = 0;
-            for (uint32_t j = 1; j <= L; ++j) {
-                const uint32_t b = B[ph * 256 + (uint32_t)((sv >> (8 * (j - 1))) & 0xFF)];
-                M = (M << 1) & b;
-                C = ((C << 1) | 1u) & b;
-                if ((int)j <= n - 1 && ((M >> (n - 1)) & 1u)) F |= 1u << (n - 1 - (int)j);
-                f |= (C >> (n - 1)) & 1u;
-            }
-            E[ph * 256 + code] = make_uint2(M | (F << 16) | (f << 31), C | (L << 16));
+            T[q * 256 + code] = (uint8_t)st;
         }
     }
 }
 
-// One byte through the automaton of phase ph (0: first word, 1: second word,
-// 2: matched).
-__device__ __forceinline__ void fsst_step(const uint32_t* B, int n1, int n2, uint32_t x, uint32_t& D,
-                                          uint32_t& ph) {
-    if (ph >= 2) return;
-    const int n = ph ? n2 : n1;
-    D = ((D << 1) | 1u) & B[ph * 256 + x];
-    if ((D >> (n - 1)) & 1u) {
-        D = 0;
-        ++ph;
-    }
-}
-
-// The string atom on FSST mini block m: returns the mask of rows that
-// contain s1 and, after its leftmost end, s2 (row 64 k + lane -> bit k).
-// Lane l takes rows 4 l .. 4 l + 3, whose codes are contiguous in the heap.
-// A lane's run of codes through a 32-byte register window x:y at heap
-// offset A (16-byte aligned, A <= pos < A + 16).  The heap is padded, so
-// the window's loads stay inside it while pos is at most the heap's end.
+// A lane's run of codes through a 48-byte register window x:y:z of the
+// heap (x at byte offset A from base, 16-byte aligned, A <= pos < A + 16):
+// a peek reads x and y only, so the load that refills z has the 16 bytes of
+// y to work through before it is waited for.  Offsets are 32-bit, relative
+// to the 16-byte-aligned start of the mini block's codes; the heap is
+// padded, so the window's loads stay inside it while pos is at most the
+// mini block's end.
 struct CodeReader {
-    cptr<uint4> hv;
-    uint64_t pos, A;
-    uint4 x, y;
-    __device__ __forceinline__ void init(const uint8_t* heap, uint64_t p) {
-        hv = (cptr<uint4>)heap;
-        pos = p;
-        A = p & ~uint64_t(15);
-        x = ld4(hv, (uint32_t)(A >> 4));
-        y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+    cptr<uint4> base;
+    uint32_t pos, A;
+    uint4 x, y, z;
+    __device__ __forceinline__ void init(const uint8_t* heap, uint64_t h0, uint32_t p) {
+        const uint64_t a0 = h0 & ~uint64_t(15);
+        base = (cptr<uint4>)(heap + a0);
+        pos = (uint32_t)(h0 - a0) + p;
+        A = pos & ~15u;
+        x = ld4(base, A >> 4);
+        y = ld4(base, (A >> 4) + 1u);
+        z = ld4(base, (A >> 4) + 2u);
     }
     // the next 4 code bytes, first in the low byte
     // (two-way selects: a four-way pick by o >> 2 compiles to a stack copy
     // of the window and an indexed load)
     __device__ __forceinline__ uint32_t peek4() const {
-        const uint32_t o = (uint32_t)(pos - A);
+        const uint32_t o = pos - A;
         const bool half = (o & 8u) != 0;
         const uint32_t a0 = half ? x.z : x.x, a1 = half ? x.w : x.y, b0 = half ? y.x : x.z;
         const uint32_t lo = __builtin_amdgcn_alignbyte(a1, a0, o & 3u);
@@ -843,12 +803,14 @@ struct CodeReader {
         if (pos - A < 16) return;
         if (pos - A < 32) {
             x = y;
+            y = z;
             A += 16;
-            y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+            z = ld4(base, (A >> 4) + 2u);
         } else {
-            A = pos & ~uint64_t(15);
-            x = ld4(hv, (uint32_t)(A >> 4));
-            y = ld4(hv, (uint32_t)(A >> 4) + 1u);
+            A = pos & ~15u;
+            x = ld4(base, A >> 4);
+            y = ld4(base, (A >> 4) + 1u);
+            z = ld4(base, (A >> 4) + 2u);
         }
     }
 };
@@ -872,73 +834,51 @@ __device__ __forceinline__ bool fsst_lengths(CC& c, int m, int lane, int nvalid,
     return (uint64_t)__builtin_amdgcn_readlane(incl, 63) == h1 - h0;
 }
 
-// fl: 256 bytes of the wave's LDS for the transposition.
-__device__ __forceinline__ uint32_t fsst_pred(CQ& Q, CC& c, CP& p, int m, int lane, int nvalid, uint8_t* fl,
+// The string atom on FSST mini block m: returns the mask of rows that
+// contain s1 and, after its leftmost end, s2 (row 64 k + lane -> bit k).
+// Lane l takes rows 4 l .. 4 l + 3, whose codes are contiguous in the heap,
+// four codes per step.  fl: 256 bytes of the wave's LDS for the
+// transposition.
+__device__ __forceinline__ uint32_t fsst_pred(CQ& Q, CC& c, int m, int lane, int nvalid, uint8_t* fl,
                                               const uint8_t* smem_shared, bool& ok) {
-    const uint8_t* T = smem_shared + Q.fs_lds_off;
-    const uint32_t* B = reinterpret_cast<const uint32_t*>(T + kFsstB);
-    const uint2* E = reinterpret_cast<const uint2*>(T + kFsstE);
-    const uint64_t* sym = reinterpret_cast<const uint64_t*>(T + kFsstSym);
-    const uint8_t* len = T + kFsstLen;
+    // The table is the first thing in the shared area (fs_lds_off == 0), so
+    // its address is a constant and a step's LDS address is one byte
+    // permute: {code, state, 0, 0}.
+    const uint8_t* T = smem_shared;
+    const uint32_t S = (uint32_t)Q.fs_states, acc = S - 1;
     uint32_t rl[4], lsum, incl;
     uint64_t h0;
     if (!fsst_lengths(c, m, lane, nvalid, rl, lsum, incl, h0)) { ok = false; return 0; }
     CodeReader R;
-    R.init(c.heap, h0 + (incl - lsum));
+    R.init(c.heap, h0, incl - lsum);
     uint32_t res = 0;
-    bool esc = false;
 #pragma unroll 1
     for (int r = 0; r < 4; ++r) {
         // (a select, not rl[r]: a dynamic index would put rl in scratch)
         uint32_t rem = r == 0 ? rl[0] : r == 1 ? rl[1] : r == 2 ? rl[2] : rl[3];
-        uint32_t D = 0, ph = 0;
+        uint32_t st = 0;
         while (rem) {
             const uint32_t q = R.peek4();
             const uint32_t nq = min(rem, 4u);
-            const uint2* Et = E + ph * 256;
-            uint2 e[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) e[j] = Et[(q >> (8 * j)) & 0xFFu];
-            const uint32_t D0 = D;
-            uint32_t hit = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool act = (uint32_t)j < nq;
-                hit |= act ? (((D << 16) | 0x80000000u) & e[j].x) : 0u;
-                const uint32_t nd = (((D << (e[j].y >> 16)) & e[j].x) | e[j].y) & 0xFFFFu;
-                D = act ? nd : D;
-            }
-            if (hit | (uint32_t)esc) {
-                // byte at a time: escapes, and a word completing in a symbol
-                D = D0;
-                for (uint32_t j = 0; j < nq && ph < 2; ++j) {
-                    const uint32_t cd = (q >> (8 * j)) & 0xFFu;
-                    if (esc) {
-                        fsst_step(B, p.n1, p.n2, cd, D, ph);
-                        esc = false;
-                    } else if (cd == 255u) {
-                        esc = true;
-                    } else {
-                        const uint32_t L = len[cd];
-                        if (L == 0) ok = false;  // a code the table does not define
-                        const uint64_t sv = sym[cd];
-                        for (uint32_t b = 0; b < L && ph < 2; ++b)
-                            fsst_step(B, p.n1, p.n2, (uint32_t)(sv >> (8 * b)) & 0xFFu, D, ph);
-                    }
-                }
-            }
+            // the states after 1, 2, 3 and 4 codes; the record may end first
+            const uint32_t s1 = T[__builtin_amdgcn_perm(st, q, 0x0c0c0400u)];
+            const uint32_t s2 = T[__builtin_amdgcn_perm(s1, q, 0x0c0c0401u)];
+            const uint32_t s3 = T[__builtin_amdgcn_perm(s2, q, 0x0c0c0402u)];
+            uint32_t s4 = T[__builtin_amdgcn_perm(s3, q, 0x0c0c0403u)];
+            // (an empty use keeps the fourth read unconditional: the compiler
+            // otherwise branches on nq around it)
+            asm volatile("" : "+v"(s4));
+            st = s1;
+            st = nq >= 2 ? s2 : st;
+            st = nq >= 3 ? s3 : st;
+            st = nq >= 4 ? s4 : st;
             // matched: the rest of the record is skipped
-            const uint32_t adv = ph >= 2 ? rem : nq;
+            const uint32_t adv = st == acc ? rem : nq;
             rem -= adv;
             R.advance(adv);
         }
-        if (ph >= 2) {
-            esc = false;
-        } else if (esc) {
-            ok = false;  // an escape without its byte
-            esc = false;
-        }
-        res |= (uint32_t)(ph >= 2) << r;
+        if (st >= S) ok = false;  // an escape without its byte, or a code the table does not define
+        res |= (uint32_t)(st == acc) << r;
     }
     // rows 4 lane + j -> rows 64 k + lane, through LDS
     reinterpret_cast<uint32_t*>(fl)[lane] =
@@ -1285,8 +1225,8 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const uint8_t* smem_share
                 ok_hdr = false;  // unreachable: the launch picks the string instantiation
                 return 0;
             } else if (kStr == 2 && Q.cols[P.col].enc == ENC_FSST) {
-                mask &= fsst_pred(Q, Q.cols[P.col], P, m, lane, nvalid, reinterpret_cast<uint8_t*>(W.offs),
-                                  smem_shared, ok_hdr);
+                mask &= fsst_pred(Q, Q.cols[P.col], m, lane, nvalid, reinterpret_cast<uint8_t*>(W.offs), smem_shared,
+                                  ok_hdr);
             } else {
                 // (the table is loaded for the plan's last atom only)
                 if (str_mode(P.n1, P.n2) == kStrShifted)
@@ -1593,7 +1533,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             }
             __syncthreads();
             load_lds_state(Q, shared_area, str_tab);
-            if (kStr == 2) fsst_load_masks(Q, shared_area);
+            if (kStr == 2) fsst_load_dfa(Q, shared_area);
             fs_chunk = -1;
             __syncthreads();
             cur = qi;
@@ -1934,7 +1874,7 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
         // pass 1: decoded lengths
         uint32_t dl[4] = {0, 0, 0, 0}, dsum = 0;
         CodeReader R;
-        R.init(C.heap, h0 + (incl - lsum));
+        R.init(C.heap, h0, incl - lsum);
         bool esc = false;
 #pragma unroll 1
         for (int r = 0; r < 4; ++r) {
@@ -1973,7 +1913,7 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
         for (uint32_t w0 = 0; w0 < dtotal; w0 += kFsstStage) {
             const uint32_t wn = min((uint32_t)kFsstStage, dtotal - w0);
             if (start < w0 + wn && start + dsum > w0) {
-                R.init(C.heap, h0 + (incl - lsum));
+                R.init(C.heap, h0, incl - lsum);
                 uint32_t d = start;  // decoded position of the next byte
                 uint32_t rem = lsum;
                 while (rem && d < w0 + wn) {

@@ -559,6 +559,36 @@ void build_str_table(DevPred& d) {
 
 inline bool is_string_enc(int32_t enc) { return enc == DPF_ENC_VARLEN || enc == DPF_ENC_FSST; }
 
+// Byte automaton of LIKE '%s1%s2%' for FSST columns: the Knuth-Morris-Pratt
+// automata of the two words in sequence.  States 0 .. n1-1 hold the length
+// of the longest prefix of s1 that ends at the current byte; completing s1
+// (its leftmost end) leads to state n1, where the search for s2 starts, and
+// states n1 .. n1+n2-1 hold n1 plus the matched prefix of s2; n1 + n2 is the
+// accept state, absorbing.  Row q holds the next state for each byte value.
+std::vector<uint8_t> seq_automaton(const uint8_t* s1, int n1, const uint8_t* s2, int n2) {
+    const int S = n1 + n2 + 1;
+    std::vector<uint8_t> D((size_t)S * 256);
+    auto word = [&](const uint8_t* w, int n, int base, int done) {
+        // t[j][x]: matched prefix length after byte x from length j (KMP)
+        std::vector<int> t((size_t)n * 256, 0);
+        t[w[0]] = 1;
+        for (int j = 1, back = 0; j < n; ++j) {
+            for (int x = 0; x < 256; ++x) t[(size_t)j * 256 + x] = t[(size_t)back * 256 + x];
+            t[(size_t)j * 256 + w[j]] = j + 1;
+            back = t[(size_t)back * 256 + w[j]];
+        }
+        for (int j = 0; j < n; ++j)
+            for (int x = 0; x < 256; ++x) {
+                const int v = t[(size_t)j * 256 + x];
+                D[(size_t)(base + j) * 256 + x] = (uint8_t)(v == n ? done : base + v);
+            }
+    };
+    word(s1, n1, 0, n1);
+    word(s2, n2, n1, n1 + n2);
+    for (int x = 0; x < 256; ++x) D[(size_t)(S - 1) * 256 + x] = (uint8_t)(S - 1);
+    return D;
+}
+
 // Translates p on column c into d.  *drop = the atom is always true.
 dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<int64_t>& in_vals, DevPred& d,
                           bool* drop) {
@@ -570,9 +600,6 @@ dpf_status translate_pred(const dpf_pred& p, const HostColumn& c, std::vector<in
         if (!is_string_enc(c.enc)) return fail(DPF_ERR_INVALID_ARG, "string predicate on a non-string column");
         if (p.n1 < 1 || p.n2 < 1 || p.n1 > kMaxWord || p.n2 > kMaxWord || !p.s1 || !p.s2)
             return fail(DPF_ERR_UNSUPPORTED, "string predicate words must have 1..32 bytes");
-        // the FSST test keeps a word's automaton state in 16 bits
-        if (c.enc == DPF_ENC_FSST && (p.n1 > kFsstMaxWordBytes || p.n2 > kFsstMaxWordBytes))
-            return fail(DPF_ERR_UNSUPPORTED, "string predicate words on an FSST column must have 1..16 bytes");
         d.kind = PK_STR;
         d.n1 = p.n1;
         d.n2 = p.n2;
@@ -893,11 +920,12 @@ void assign_lds(dpf_plan p, int32_t budget) {
     if (budget < 0) budget = kDefaultLdsHash;
     std::vector<int> order;
     int32_t off = 0;
-    // an FSST atom's code tables come first: they are not optional
+    // an FSST atom's code table comes first (the kernel takes its address as
+    // the start of the shared area): it is not optional
     q.fs_lds_off = -1;
     if (q.fs_pred >= 0) {
         q.fs_lds_off = off;
-        off += kFsstLdsBytes;
+        off += (int32_t)align_up((size_t)(2 * q.fs_states + 1) * 256, 16);
     }
     // A probe that needs no payload only asks membership: its key-range
     // bitmap (when it has one) is the structure placed in LDS.
@@ -1078,12 +1106,16 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     q.nint_preds = q.npreds;
     for (auto& d : strs) q.preds[q.npreds++] = d;
     q.has_str = !strs.empty();
-    // the fused kernel keeps the code tables of one FSST atom per plan
+    // the fused kernel keeps the code table of one FSST atom per plan
     q.fs_pred = -1;
+    std::vector<uint8_t> fs_dfa;
     for (int i = q.nint_preds; i < q.npreds; ++i) {
         if (desc->cols[q.preds[i].col]->host.enc != DPF_ENC_FSST) continue;
         if (q.fs_pred >= 0) return bail(fail(DPF_ERR_UNSUPPORTED, "a plan takes at most one FSST string predicate"));
         q.fs_pred = i;
+        const DevPred& d = q.preds[i];
+        fs_dfa = seq_automaton(d.s1, d.n1, d.s2, d.n2);
+        q.fs_states = d.n1 + d.n2 + 1;
     }
     std::copy(in_vals.begin(), in_vals.end(), q.in_vals);
 
@@ -1234,11 +1266,13 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     p->nlive = prune_mb ? (int64_t)live.size() : p->nblocks;
 
     // device memory: [DevQuery][agg table][status][counters][live blocks]
+    // [FSST byte automaton]
     const size_t q_off = 0, agg_off = align_up(sizeof(DevQuery), 256);
     const size_t agg_bytes = (size_t)q.ngroups * q.nacc * 8;
     const size_t st_off = align_up(agg_off + agg_bytes, 256), cnt_off = st_off + 256;
     const size_t live_off = align_up(cnt_off + (size_t)kCounterWords * 4, 256);
-    p->dmem_bytes = live_off + live.size() * 4;
+    const size_t dfa_off = align_up(live_off + live.size() * 4, 256);
+    p->dmem_bytes = dfa_off + fs_dfa.size();
     p->dmem = ctx->alloc_mem(p->dmem_bytes, DPF_MEM_HBM);
     if (!p->dmem) return bail(fail(DPF_ERR_OOM, "plan workspace"));
     p->host_out_bytes = (2 + (size_t)q.ngroups * (1 + q.nacc)) * 8;
@@ -1256,18 +1290,24 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     q.live = prune_mb ? (const int32_t*)(d + live_off) : nullptr;
     q.nlive = (int32_t)live.size();
     q.prune_mb = prune_mb;
+    q.fs_dfa = fs_dfa.empty() ? nullptr : d + dfa_off;
     // Asynchronous upload on the context's upload stream: a fill kernel
     // zeroes the group table, status and queue counters, and the descriptor
     // and block list are copied from pinned staging.  The first executions
     // wait for the event (see wait_uploads); nothing here blocks the host.
     const size_t stage_q = align_up(sizeof(DevQuery), 256);
-    p->staging = ctx->alloc_mem(stage_q + live.size() * 4, DPF_MEM_HOST_MAPPED);
+    const size_t stage_dfa = align_up(stage_q + live.size() * 4, 256);
+    p->staging = ctx->alloc_mem(stage_dfa + fs_dfa.size(), DPF_MEM_HOST_MAPPED);
     if (!p->staging) return bail(fail(DPF_ERR_OOM, "plan staging"));
     std::memcpy(p->staging, &q, sizeof q);
     if (!live.empty()) std::memcpy((uint8_t*)p->staging + stage_q, live.data(), live.size() * 4);
+    if (!fs_dfa.empty()) std::memcpy((uint8_t*)p->staging + stage_dfa, fs_dfa.data(), fs_dfa.size());
     hipError_t e = launch_fill_i32((int32_t*)(d + agg_off), 0, (int64_t)((live_off - agg_off) / 4), ctx->upload);
     if (e == hipSuccess && !live.empty())
         e = hipMemcpyAsync(d + live_off, (uint8_t*)p->staging + stage_q, live.size() * 4, hipMemcpyHostToDevice,
+                           ctx->upload);
+    if (e == hipSuccess && !fs_dfa.empty())
+        e = hipMemcpyAsync(d + dfa_off, (uint8_t*)p->staging + stage_dfa, fs_dfa.size(), hipMemcpyHostToDevice,
                            ctx->upload);
     if (e == hipSuccess) e = hipMemcpyAsync(p->dq, p->staging, sizeof q, hipMemcpyHostToDevice, ctx->upload);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);

@@ -1,12 +1,12 @@
 """GPU parity for FSST string columns (paper Sections 3.4.2 and 4.1) against
 the unchanged oracle, which evaluates the string predicate on the raw
-strings: the fused kernel's symbol-level matcher and the fragmented path's
+strings: the fused kernel's code-level automaton and the fragmented path's
 two-pass record decode, on the string workload's comments (ragged sizes,
 small chunks so that work items cross chunk boundaries, host-mapped
 placement), on dense small alphabets with words planted at every position
 (word completions inside symbols, the switch to the second word inside a
-symbol), on arbitrary bytes (escape codes), and in a batch beside a VARLEN
-plan."""
+symbol, words up to 32 bytes), on arbitrary bytes (escape codes), and in a
+batch beside a VARLEN plan."""
 import numpy as np
 import pytest
 
@@ -127,16 +127,47 @@ def test_batch_with_varlen_plan(ctx):
 
 
 def test_fsst_word_limits(ctx):
-    """Words of up to 16 bytes on an FSST column; longer words, and a second
-    FSST predicate in one plan, are refused."""
+    """Words of up to 32 bytes on an FSST column (the longest give the
+    largest code table, 131 rows); a longer word, and a second FSST
+    predicate in one plan, are refused."""
     from paper_2605_10511_amd import dpf
     t = {"s": to_strings([b"abc"] * 300), "u": to_strings([b"abd"] * 300), "g": np.zeros(300, np.int32)}
     db = G.make_db(ctx, {"t": t}, {"t": {"s": "FSST", "u": "FSST"}})
     base = {"fact": "t", "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
     with pytest.raises(dpf.DpfError):
-        db.plan(dict(base, filters=[{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": b"a" * 17, "s2": b"b"}]))
+        db.plan(dict(base, filters=[{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": b"a" * 33, "s2": b"b"}]))
     with pytest.raises(dpf.DpfError):
         db.plan(dict(base, filters=[{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": b"a", "s2": b"b"},
                                     {"col": "u", "op": "STR_CONTAINS_SEQ", "s1": b"a", "s2": b"d"}]))
     spec = dict(base, filters=[{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": b"a", "s2": b"c"}])
     G.assert_same(G.run_gpu(db, spec), oracle.run(spec, {"t": t}), "abc")
+
+
+@pytest.mark.parametrize("n1,n2", [(17, 5), (24, 24), (32, 32), (31, 1)])
+def test_long_words(ctx, n1, n2):
+    """Words of 17..32 bytes planted in text of the same alphabet."""
+    G.say("fsst long words", n1, n2)
+    rng = np.random.default_rng(1300 + n1 * 33 + n2)
+    alpha = np.frombuffer(b"abc ", np.uint8)
+    s1 = bytes(rng.choice(alpha[:3], n1))
+    s2 = bytes(rng.choice(alpha[:3], n2))
+    n = 8000
+    items = []
+    for i in range(n):
+        s = bytearray(rng.choice(alpha, int(rng.integers(0, 120))).tobytes())
+        r = rng.random()
+        if r < 0.3:
+            a = int(rng.integers(0, len(s) + 1))
+            s[a:a] = s1
+            b = int(rng.integers(a + n1, len(s) + 1))
+            s[b:b] = s2
+        elif r < 0.4:
+            s = bytearray(s1[:-1] + s2 + s1)  # s1 only after s2, and a near miss
+        items.append(bytes(s))
+    t = {"s": to_strings(items), "g": (np.arange(n) % 4).astype(np.int32)}
+    db = G.make_db(ctx, {"t": t}, {"t": {"s": "FSST"}}, chunk_rows=1024)
+    spec = {"fact": "t", "filters": [{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": s1, "s2": s2}],
+            "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
+    want = oracle.run(spec, {"t": t})
+    for mode in ("FUSED", "FRAGMENTED"):
+        G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{n1}/{n2} {mode}")
