@@ -74,6 +74,20 @@ def measured_traffic(workload: str):
         return None
 
 
+def copy_probe(args):
+    """A plain copy of --copy-probe MiB (torch add), the calibration dispatch
+    of the HBM-traffic counter passes."""
+    if not args.copy_probe:
+        return
+    import torch
+    n = args.copy_probe * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.add(a, 0, out=b)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: read {n * 4} B, wrote {n * 4} B")
+
+
 def host_threads() -> int:
     """Host threads the CPU baseline uses: the job's CPU share (the thread
     count the environment sets for OpenMP-style pools, else the CPUs this
@@ -228,6 +242,8 @@ def main():
                     help="also run a plain copy of this many MiB (PMC scale reference)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the bandwidth-ceiling microbenchmarks")
     ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache trials")
+    ap.add_argument("--encodings", default="VARLEN,FSST", help="fsst: comment encodings to run")
+    ap.add_argument("--placements", default="HBM,HOST_MAPPED", help="fsst: placements to run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the fused path on a single MI355X "
@@ -330,13 +346,7 @@ def main():
                     protocol="10 trials, each after writing a 1 GiB buffer (evicts L2 and the Infinity Cache)")
         log(f"[bench] cold: mean {cold['mean_ms']:.3f} ms, median {cold['median_ms']:.3f}, min {cold['min_ms']:.3f}")
 
-    if args.copy_probe:
-        n = args.copy_probe * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        torch.add(a, 0, out=b)
-        torch.cuda.synchronize()
-        log(f"[bench] copy probe: read {n * 4} B, wrote {n * 4} B")
+    copy_probe(args)
 
     cpu = None
     parity = None
@@ -653,8 +663,10 @@ def bench_chain(args):
         want, cpu = oracle_baseline(spec, tables, n, f"the {n:,}-row lineitem pipeline with both builds")
         parity = bool(np.array_equal(want, got))
         log(f"[chain] GPU result {'==' if parity else '!='} oracle")
+    copy_probe(args)
     ms = res["FUSED"][0]
     achieved = alg / (ms * 1e-3) / 1e9
+    traffic = measured_traffic("chain")
     print(json.dumps({
         "metric": METRIC, "value": n / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -663,8 +675,9 @@ def bench_chain(args):
                                f"table and aggregation by (region, priority)", "rows": n},
         "chained_build_ms": min(builds), "chained_entries": entries,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": "fused_kernel", "kernel_ms": ms,
-                     "algorithmic_bytes": alg},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_gbps": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
+                     "kernel": "fused_kernel", "kernel_ms": ms, "algorithmic_bytes": alg},
         "fragmented": {"ms": res["FRAGMENTED"][0], "matches_fused": bool(np.array_equal(res["FRAGMENTED"][1], got)),
                        "speedup_of_fused": res["FRAGMENTED"][0] / ms},
         "cpu_baseline": cpu, "parity_vs_oracle": parity}), flush=True)
@@ -682,10 +695,10 @@ def bench_fsst(args):
     ctx = dpf.Context(0)
     stream = torch.cuda.current_stream()
     runs, results = {}, {}
-    for enc in ("VARLEN", "FSST"):
+    for enc in args.encodings.split(","):
         e = dict(encs["fact"])
         e["comment"] = enc
-        for place in ("HBM", "HOST_MAPPED"):
+        for place in args.placements.split(","):
             db = dpf.Database(ctx)
             t0 = time.time()
             db.add_table("fact", tables["fact"], e, placement=place)
@@ -716,7 +729,8 @@ def bench_fsst(args):
                     f"({nbytes / nrows:.2f} B/row; comment {runs[key]['comment_bytes'] / nrows:.2f} B/row)")
             plan.release()
             del db
-    ref = results["varlen_hbm_fused"]
+    copy_probe(args)
+    ref = next(iter(results.values()))
     same = all(np.array_equal(ref, r) for r in results.values())
     cpu, parity = None, None
     if not args.no_oracle:
@@ -725,6 +739,8 @@ def bench_fsst(args):
         log(f"[fsst] FSST result {'==' if parity else '!='} oracle")
     f = runs["fsst_hbm"]
     ms = f["fused_ms"]
+    traffic = measured_traffic("fsst")
+    full = all(k in runs for k in ("varlen_hbm", "varlen_host_mapped", "fsst_host_mapped"))
     print(json.dumps({
         "metric": METRIC, "value": nrows / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -732,13 +748,15 @@ def bench_fsst(args):
         "config": {"workload": f"wide string query, comment column FSST vs VARLEN ({nrows:,} rows), "
                                f"HBM and host-mapped", "rows": nrows},
         "roofline": {"bound": "hbm", "achieved": f["fused_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": f["fused_gbps"] / HBM_PEAK_GBPS, "traffic": None, "kernel": "fused_kernel",
+                     "frac": f["fused_gbps"] / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_gbps": (traffic / (ms * 1e-3) / 1e9) if traffic else None, "kernel": "fused_kernel",
                      "kernel_ms": ms, "algorithmic_bytes": f["bytes"]},
         "runs": runs, "all_results_equal": same,
         "fsst_vs_varlen": {"bytes": runs["varlen_hbm"]["bytes"] / f["bytes"],
                            "fused_hbm_speedup": runs["varlen_hbm"]["fused_ms"] / ms,
                            "fused_host_speedup": runs["varlen_host_mapped"]["fused_ms"] / runs["fsst_host_mapped"]["fused_ms"],
-                           "fragmented_hbm_speedup": runs["varlen_hbm"]["fragmented_ms"] / f["fragmented_ms"]},
+                           "fragmented_hbm_speedup": runs["varlen_hbm"]["fragmented_ms"] / f["fragmented_ms"]}
+        if full else None,
         "cpu_baseline": cpu, "parity_vs_oracle": parity}), flush=True)
 
 

@@ -1258,6 +1258,21 @@ __device__ __forceinline__ uint32_t filter_tile(CQ& Q, const uint8_t* smem_share
     return mask;
 }
 
+// Rows of mask (row 64 k + lane -> bit k) of mini block m whose first
+// probe finds its key.
+__device__ __forceinline__ uint32_t member_tile(CQ& Q, const uint8_t* smem_shared, int m, int lane, uint32_t mask,
+                                                bool& ok_hdr) {
+    CPR& P0 = Q.probes[0];
+    CC& fc = Q.cols[P0.fk_col];
+    int64_t fk[4];
+    ok_hdr &= decode_dense(fc, m, lane, fk);
+    if (fc.enc == ENC_DICT)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
+    return P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
+                             : hash_member4<false>(P0.h, smem_shared, fk, mask);
+}
+
 template <int kStr>
 __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                              int m, int lane, int& npend, bool& ok_hdr) {
@@ -1277,10 +1292,15 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsign
     }
     if (npreds == 0) return;  // probes without predicates: semi_tiles handles those plans
     // (an FSST atom is never the eager one: its plan has fs_pred >= 0)
-    const uint32_t mask =
+    uint32_t mask =
         Q.nint_preds == npreds - 1 && Q.preds[npreds - 1].kind == PK_STR && Q.fs_pred < 0
             ? (kStr ? filter_tile<true, kStr>(Q, smem_shared, W, m, lane, nvalid, ok_hdr) : (ok_hdr = false, 0u))
             : filter_tile<false, kStr>(Q, smem_shared, W, m, lane, nvalid, ok_hdr);
+    // The first (most selective) probe's membership test joins stage A: its
+    // foreign keys are decoded for the whole mini block with coalesced
+    // loads, so stage B gets only the rows that find their key (and probes
+    // them again for payloads), not every row that passed the filters.
+    if (Q.nprobes > 0 && __ballot(mask != 0)) mask = member_tile(Q, smem_shared, m, lane, mask, ok_hdr);
     queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
