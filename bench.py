@@ -243,6 +243,7 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the bandwidth-ceiling microbenchmarks")
     ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache trials")
     ap.add_argument("--encodings", default="VARLEN,FSST", help="fsst: comment encodings to run")
+    ap.add_argument("--fractions", default="0.01,0.05,0.25,0.5,0.75,1.0", help="sweep: date cutoffs (fraction of dates)")
     ap.add_argument("--placements", default="HBM,HOST_MAPPED", help="fsst: placements to run")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -569,7 +570,7 @@ def bench_sweep(args):
     db.add_table("fact", t, W.FA_ENCODINGS)
     stream = torch.cuda.current_stream()
     points = []
-    for frac in (0.01, 0.05, 0.25, 0.5, 0.75, 1.0):
+    for frac in (float(x) for x in args.fractions.split(",")):
         spec = W.fa_query(date_lt=max(1, int(round(W.NDATES * frac))))
         plan = db.plan(spec)
         got = {}

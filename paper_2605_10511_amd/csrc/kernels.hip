@@ -2040,36 +2040,55 @@ __global__ __launch_bounds__(kBlock) void frag_filter_str(const DevQuery* __rest
 
 // flags -> row list (order not preserved; aggregation is order-free).  One
 // global atomic per workgroup step of 1024 rows.
+// Output space is reserved once per tile of kFragTile rows (16 per thread):
+// one device-scope atomic on the list's counter per tile.  With one per
+// 64- or 1,024-row step the atomics on that single counter serialised the
+// kernels.
+constexpr int kFragRows = 16;
+constexpr int kFragTile = kBlock * kFragRows;
+
+// Per wave: its survivors' count from the per-lane keep bits (bit k: row k
+// of the lane), then the tile's reservation; returns the wave's first slot.
+__device__ __forceinline__ unsigned long long frag_reserve(uint32_t keep, unsigned long long* count, int lane,
+                                                           int wave) {
+    __shared__ uint32_t wcnt[kWaves];
+    __shared__ unsigned long long base_s;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kFragRows; ++k) c += (uint32_t)__popcll(__ballot((keep >> k) & 1u));
+    if (lane == 0) wcnt[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; ++w) { const uint32_t x = wcnt[w]; wcnt[w] = t; t += x; }
+        base_s = t ? atomicAdd(count, (unsigned long long)t) : 0;
+    }
+    __syncthreads();
+    const unsigned long long o = base_s + wcnt[wave];
+    __syncthreads();  // wcnt and base_s are rewritten by the next tile
+    (void)lane;
+    return o;
+}
+
 __global__ __launch_bounds__(kBlock) void frag_compact(const DevQuery* __restrict__ q, const uint8_t* flags,
                                                        FragRow* rows, unsigned long long* count) {
-    __shared__ uint32_t wcnt[kWaves + 1];
-    __shared__ unsigned long long base_s;
     CQ& Q = *ro(q);
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    for (int64_t b0 = (int64_t)blockIdx.x * 1024; b0 < Q.nrows; b0 += (int64_t)gridDim.x * 1024) {
-        bool f[4];
-        uint32_t c = 0;
-        uint64_t bal[4];
-        for (int k = 0; k < 4; ++k) {
-            int64_t r = b0 + wave * 256 + 64 * k + lane;
-            f[k] = r < Q.nrows && flags[r];
-            bal[k] = __ballot(f[k]);
-            c += (uint32_t)__popcll(bal[k]);
+    for (int64_t t0 = (int64_t)blockIdx.x * kFragTile; t0 < Q.nrows; t0 += (int64_t)gridDim.x * kFragTile) {
+        uint32_t keep = 0;
+#pragma unroll
+        for (int k = 0; k < kFragRows; ++k) {
+            const int64_t r = t0 + (int64_t)k * kBlock + threadIdx.x;
+            keep |= (uint32_t)(r < Q.nrows && flags[r]) << k;
         }
-        if (lane == 0) wcnt[wave] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kWaves; ++w) { uint32_t x = wcnt[w]; wcnt[w] = t; t += x; }
-            base_s = t ? atomicAdd(count, (unsigned long long)t) : 0;
+        unsigned long long o = frag_reserve(keep, count, lane, wave);
+#pragma unroll
+        for (int k = 0; k < kFragRows; ++k) {
+            const bool f = (keep >> k) & 1u;
+            const uint64_t b = __ballot(f);
+            if (f) rows[o + bits_below(b)] = (FragRow)(t0 + (int64_t)k * kBlock + threadIdx.x);
+            o += (uint32_t)__popcll(b);
         }
-        __syncthreads();
-        unsigned long long o = base_s + wcnt[wave];
-        for (int k = 0; k < 4; ++k) {
-            if (f[k]) rows[o + bits_below(bal[k])] = (FragRow)(b0 + wave * 256 + 64 * k + lane);
-            o += (uint32_t)__popcll(bal[k]);
-        }
-        __syncthreads();
     }
 }
 
@@ -2090,33 +2109,39 @@ __global__ __launch_bounds__(kBlock) void frag_probe(const DevQuery* __restrict_
                                                      const FragBuffers fb, int src, int npay_before) {
     CQ& Q = *ro(q);
     CPR& P = Q.probes[j];
-    const int lane = lane_id();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int64_t n = (int64_t)*nin;
-    for (int64_t b0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~63ll; b0 < n;
-         b0 += (int64_t)gridDim.x * blockDim.x) {
-        int64_t e = b0 + lane;
-        bool act = e < n;
-        int slot = -1;
-        const FragRow r = act ? rin[e] : 0u;
-        if (act) {
-            int64_t fk = fkvals[(int64_t)r];
-            CC& fc = Q.cols[P.fk_col];
-            bool okd = true;
-            if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, okd);
-            // the same bitmap pre-test as the fused kernel's stage B
-            if (!P.h.bits || bitmap_has_global(P.h, fk)) slot = hash_find<false>(P.h, nullptr, fk);
+    CC& fc = Q.cols[P.fk_col];
+    for (int64_t t0 = (int64_t)blockIdx.x * kFragTile; t0 < n; t0 += (int64_t)gridDim.x * kFragTile) {
+        uint32_t keep = 0;
+        int slot[kFragRows];
+#pragma unroll
+        for (int k = 0; k < kFragRows; ++k) {
+            const int64_t e = t0 + (int64_t)k * kBlock + threadIdx.x;
+            slot[k] = -1;
+            if (e < n) {
+                int64_t fk = fkvals[(int64_t)rin[e]];
+                bool okd = true;
+                if (fc.enc == ENC_DICT) fk = dict_value(fc, fk, okd);
+                // the same bitmap pre-test as the fused kernel's stage B
+                if (!P.h.bits || bitmap_has_global(P.h, fk)) slot[k] = hash_find<false>(P.h, nullptr, fk);
+            }
+            keep |= (uint32_t)(slot[k] >= 0) << k;
         }
-        bool keep = slot >= 0;
-        uint64_t bal = __ballot(keep);
-        unsigned long long base = 0;
-        if (lane == 0 && bal) base = atomicAdd(nout, (unsigned long long)__popcll(bal));
-        base = __shfl(base, 0, kWave);
-        if (keep) {
-            unsigned long long o = base + bits_below(bal);
-            rout[o] = r;
-            for (int t = 0; t < npay_before; ++t) fb.pay[1 - src][t][o] = fb.pay[src][t][e];
-            for (int k = 0; k < P.h.npay; ++k)
-                fb.pay[1 - src][npay_before + k][o] = hash_payload<false>(P.h, nullptr, k, slot);
+        unsigned long long o = frag_reserve(keep, nout, lane, wave);
+#pragma unroll
+        for (int k = 0; k < kFragRows; ++k) {
+            const bool f = (keep >> k) & 1u;
+            const uint64_t b = __ballot(f);
+            if (f) {
+                const int64_t e = t0 + (int64_t)k * kBlock + threadIdx.x;
+                const unsigned long long w = o + bits_below(b);
+                rout[w] = rin[e];
+                for (int t = 0; t < npay_before; ++t) fb.pay[1 - src][t][w] = fb.pay[src][t][e];
+                for (int p = 0; p < P.h.npay; ++p)
+                    fb.pay[1 - src][npay_before + p][w] = hash_payload<false>(P.h, nullptr, p, slot[k]);
+            }
+            o += (uint32_t)__popcll(b);
         }
     }
 }
