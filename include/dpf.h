@@ -200,7 +200,12 @@ enum {
     DPF_OP_BETWEEN,         /* a <= x <= b                                        */
     DPF_OP_IN,              /* x equals one of in_values[0..n_in), n_in <= 64      */
     DPF_OP_STR_CONTAINS_SEQ /* s1 occurs and s2 occurs at or after its end
-                               (LIKE '%s1%s2%'); 1 <= n1, n2 <= 32 bytes          */
+                               (LIKE '%s1%s2%'); 1 <= n1, n2 <= 32 bytes; on a
+                               VARLEN or FSST column.  A plan takes at most one
+                               such atom on an FSST column (DPF_ERR_UNSUPPORTED
+                               otherwise): the fused kernel keeps one code
+                               table of (2 (n1 + n2 + 1) + 1) x 256 bytes per
+                               workgroup in LDS (paper Sections 3.4.2, 4.1)   */
 };
 typedef struct {
     int32_t col; /* index into the column array of the enclosing description */

@@ -649,6 +649,9 @@ __device__ __forceinline__ uint32_t str_finish(CC& c, CP& p, int lane, int nvali
                 const uint32_t y = e[wd] ^ __builtin_amdgcn_alignbit(e[wd], e[wd], rot);
                 t[wd] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(L.tab) + (y & 0x7Cu));
             }
+            // one wave vote for the four words: hits are rare
+            if (!__builtin_amdgcn_ballot_w64((t[0] == e[0]) | (t[1] == e[1]) | (t[2] == e[2]) | (t[3] == e[3])))
+                continue;
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
                 const bool h = t[wd] == e[wd];
