@@ -171,3 +171,48 @@ def test_long_words(ctx, n1, n2):
     want = oracle.run(spec, {"t": t})
     for mode in ("FUSED", "FRAGMENTED"):
         G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{n1}/{n2} {mode}")
+
+
+def test_pruned_chunks_and_graph_replay(ctx):
+    """FSST plans whose date cutoff prunes most chunks (work items then map
+    onto the surviving blocks, each crossing the code-table rebuild at its
+    chunk), in one launch beside VARLEN and filter-aggregate plans, eagerly
+    and replayed from a HIP graph three times with eager work in between;
+    every result against the oracle."""
+    import torch
+    from paper_2605_10511_amd import dpf
+    G.say("fsst pruned chunks, graph replay")
+    t = W.wide_table(300_000, seed=2)
+    w1, w2, vocab = W.wide_words(2)
+    dbf = G.make_db(ctx, {"fact": t}, {"fact": _enc()}, chunk_rows=4096)
+    dbv = G.make_db(ctx, {"fact": t}, {"fact": W.WIDE_ENCODINGS}, chunk_rows=4096)
+    specs = [W.wide_query(w1, w2, date_lt=300), W.wide_query(vocab[4][:3], vocab[6][:2], date_lt=1200),
+             W.wide_query(b"e", b"a", date_lt=2556), W.wide_query(w1, w2, date_lt=300)]
+    plans = [dbf.plan(specs[0]), dbf.plan(specs[1]), dbf.plan(specs[2]), dbv.plan(specs[3])]
+    assert plans[0].blocks()[0] < plans[0].blocks()[1]  # chunks were pruned
+    wants = [oracle.run(sp, {"fact": t}) for sp in specs]
+    res = dpf.execute(ctx, plans)
+    torch.cuda.synchronize()
+    for i, w in enumerate(wants):
+        G.assert_same(res.get(i), w, f"eager plan {i}")
+    res.release()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            r = dpf.execute(ctx, plans, stream=s)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for i, w in enumerate(wants):
+            G.assert_same(r.get(i), w, f"replay {k} plan {i}")
+        e = dpf.execute(ctx, plans[k:k + 2])
+        torch.cuda.synchronize()
+        for j in range(2):
+            G.assert_same(e.get(j), wants[k + j], f"eager after replay {k}, plan {k + j}")
+        e.release()
+    r.release()
+    del g
+    for p in plans:
+        p.release()
