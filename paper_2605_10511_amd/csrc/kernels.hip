@@ -801,6 +801,15 @@ struct CodeReader {
         const uint32_t hi = __builtin_amdgcn_alignbyte(b0, a1, o & 3u);
         return (o & 4u) ? hi : lo;
     }
+    // the next 8 code bytes (a: the first four)
+    __device__ __forceinline__ void peek8(uint32_t& a, uint32_t& b) const {
+        const uint32_t o = pos - A;
+        const bool half = (o & 8u) != 0, q = (o & 4u) != 0;
+        const uint32_t B0 = half ? x.z : x.x, B1 = half ? x.w : x.y, B2 = half ? y.x : x.z, B3 = half ? y.y : x.w;
+        const uint32_t c0 = q ? B1 : B0, c1 = q ? B2 : B1, c2 = q ? B3 : B2;
+        a = __builtin_amdgcn_alignbyte(c1, c0, o & 3u);
+        b = __builtin_amdgcn_alignbyte(c2, c1, o & 3u);
+    }
     __device__ __forceinline__ void advance(uint32_t n) {
         pos += n;
         if (pos - A < 16) return;
@@ -1853,9 +1862,16 @@ __global__ __launch_bounds__(kBlock) void frag_decode_str(const DevQuery* __rest
 // records in parallel into an LDS staging window, copied out with
 // coalesced stores (a mini block larger than the window takes several
 // windows).  Each wave takes a contiguous run of mini blocks and keeps the
-// symbol table of the current chunk in its LDS.
-constexpr int kFsstStage = 8192;
-constexpr size_t kFsstDecodeWaveBytes = 256 * 8 + 256 + kFsstStage;
+// symbol table of the current chunk in its LDS.  Both passes take eight
+// codes a step, so that their table reads are issued together.  The window
+// (7.5 KiB, above the 6.8 KiB that 256 rows of the string workload's
+// comments decode to) lets four workgroups share a CU's LDS.
+constexpr int kFsstStage = 7680;
+// + 16: the spill of the last 8-byte symbol write, and the copy-out's
+// read-ahead dword
+constexpr size_t kFsstDecodeWaveBytes = 256 * 8 + 256 + kFsstStage + 16;
+// an 8-byte store at any byte address (gfx950's LDS takes unaligned access)
+typedef uint64_t u64_ua __attribute__((aligned(1)));
 
 __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __restrict__ q, int c, int64_t* off,
                                                            uint8_t* bytes) {
@@ -1884,8 +1900,10 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int e = 64 * j + lane;
-                sym[e] = ((cptr<uint64_t>)tab)[e];
-                len[e] = e < 255 ? (uint8_t)min((uint32_t)tab[256 * 8 + e], 8u) : (uint8_t)0;
+                const uint32_t le = e < 255 ? min((uint32_t)tab[256 * 8 + e], 8u) : 0u;
+                // bytes past a symbol's length are zero in LDS (code 255: none)
+                sym[e] = ((cptr<uint64_t>)tab)[e] & (le >= 8u ? ~0ull : (1ull << (8 * le)) - 1ull);
+                len[e] = (uint8_t)le;
             }
             wave_lds_sync();
         }
@@ -1894,31 +1912,42 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
         if (!fsst_lengths(C, m, lane, nvalid, rl, lsum, incl, h0)) { ok = false; continue; }
         const uint64_t d0 = ro(C.doff)[m], d1 = ro(C.doff)[m + 1];
         if (!(d0 <= d1 && d1 <= C.str_bytes)) { ok = false; continue; }
-        // pass 1: decoded lengths
-        uint32_t dl[4] = {0, 0, 0, 0}, dsum = 0;
+        // pass 1: decoded lengths, the lane's four rows' codes as one run,
+        // eight codes a step (a literal counts 1 byte; the bytes before each
+        // row boundary are summed on the side).  A code of length 0 and an
+        // escape as the lane's last code mark the column corrupt.
         CodeReader R;
         R.init(C.heap, h0, incl - lsum);
         bool esc = false;
-#pragma unroll 1
-        for (int r = 0; r < 4; ++r) {
-            uint32_t rem = r == 0 ? rl[0] : r == 1 ? rl[1] : r == 2 ? rl[2] : rl[3], n = 0;
-            while (rem) {
-                const uint32_t qd = R.peek4(), nq = min(rem, 4u);
-                for (uint32_t j = 0; j < nq; ++j) {
-                    const uint32_t cd = (qd >> (8 * j)) & 0xFFu;
-                    if (esc) { n += 1; esc = false; }
-                    else if (cd == 255u) esc = true;
-                    else if (len[cd] == 0) ok = false;
-                    else n += len[cd];
-                }
-                rem -= nq;
-                R.advance(nq);
-            }
-            if (esc) { ok = false; esc = false; }
+        const uint32_t c1 = rl[0], c2 = c1 + rl[1], c3 = c2 + rl[2];
+        uint32_t n = 0, n1 = 0, n2 = 0, n3 = 0;
+        for (uint32_t i = 0; i < lsum;) {
+            uint32_t qa, qb;
+            R.peek8(qa, qb);
+            const uint32_t nq = min(lsum - i, 8u);
+            uint32_t l[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) dl[j] = j == r ? n : dl[j];
-            dsum += n;
+            for (int j = 0; j < 8; ++j) l[j] = len[((j < 4 ? qa : qb) >> (8 * (j & 3))) & 0xFFu];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t cd = ((j < 4 ? qa : qb) >> (8 * (j & 3))) & 0xFFu;
+                const bool act = (uint32_t)j < nq;
+                const bool lit = esc;
+                ok = ok && !(act && !lit && cd != 255u && l[j] == 0);
+                const uint32_t cb = act ? (lit ? 1u : l[j]) : 0u;
+                const uint32_t k = i + j;
+                n += cb;
+                n1 += k < c1 ? cb : 0u;
+                n2 += k < c2 ? cb : 0u;
+                n3 += k < c3 ? cb : 0u;
+                esc = act ? (!lit && cd == 255u) : esc;
+            }
+            i += nq;
+            R.advance(nq);
         }
+        if (esc) { ok = false; esc = false; }
+        const uint32_t dl[4] = {n1, n2 - n1, n3 - n2, n - n3};
+        const uint32_t dsum = n;
         const uint32_t dincl = wave_incl_scan_u32(dsum);
         const uint32_t dtotal = __builtin_amdgcn_readlane(dincl, 63);
         if ((uint64_t)dtotal != d1 - d0) { ok = false; continue; }
@@ -1932,28 +1961,44 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
                 o += dl[j];
             }
         }
-        // pass 2: decode window by window
+        // pass 2: decode window by window.  A symbol is stored as one
+        // unaligned 8-byte LDS write (its padding bytes are overwritten by
+        // the next symbol); a lane's last writes can spill up to 7 zero bytes
+        // into the next lane's first bytes, so after the window every lane
+        // writes its first 7 bytes again, exactly.
+        const uint32_t dend = start + dsum;
         for (uint32_t w0 = 0; w0 < dtotal; w0 += kFsstStage) {
             const uint32_t wn = min((uint32_t)kFsstStage, dtotal - w0);
-            if (start < w0 + wn && start + dsum > w0) {
+            const uint32_t wend = w0 + wn;
+            const bool here = start < wend && dend > w0;
+            if (here) {
                 R.init(C.heap, h0, incl - lsum);
                 uint32_t d = start;  // decoded position of the next byte
                 uint32_t rem = lsum;
-                while (rem && d < w0 + wn) {
-                    const uint32_t qd = R.peek4(), nq = min(rem, 4u);
-                    for (uint32_t j = 0; j < nq; ++j) {
-                        const uint32_t cd = (qd >> (8 * j)) & 0xFFu;
-                        if (esc) {
-                            if (d - w0 < wn) stage[d - w0] = (uint8_t)cd;
-                            d += 1;
-                            esc = false;
-                        } else if (cd == 255u) {
-                            esc = true;
-                        } else {
-                            const uint32_t L = len[cd];
-                            const uint64_t sv = sym[cd];
-                            for (uint32_t b = 0; b < L; ++b)
-                                if (d + b - w0 < wn) stage[d + b - w0] = (uint8_t)(sv >> (8 * b));
+                while (rem && d < wend) {
+                    uint32_t qa, qb;
+                    R.peek8(qa, qb);
+                    const uint32_t nq = min(rem, 8u);
+                    uint64_t sv[8];
+                    uint32_t l[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint32_t cd = ((j < 4 ? qa : qb) >> (8 * (j & 3))) & 0xFFu;
+                        sv[j] = sym[cd];
+                        l[j] = len[cd];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        if ((uint32_t)j < nq) {
+                            const uint32_t cd = ((j < 4 ? qa : qb) >> (8 * (j & 3))) & 0xFFu;
+                            const uint32_t L = esc ? 1u : l[j];
+                            const uint64_t v = esc ? (uint64_t)cd : sv[j];
+                            esc = !esc && cd == 255u;
+                            if (d - w0 < wn) {
+                                *reinterpret_cast<u64_ua*>(stage + (d - w0)) = v;
+                            } else if (d < w0 && d + L > w0) {  // a symbol across the window's start
+                                for (uint32_t b = w0 - d; b < L; ++b) stage[d + b - w0] = (uint8_t)(v >> (8 * b));
+                            }
                             d += L;
                         }
                     }
@@ -1963,8 +2008,43 @@ __global__ __launch_bounds__(kBlock) void frag_decode_fsst(const DevQuery* __res
                 esc = false;
             }
             wave_lds_sync();
+            // the lane's first bytes (at most 7), which the previous lanes'
+            // spill may have zeroed, decoded again and stored byte by byte
+            if (here && start >= w0) {
+                const uint32_t hend = min(min(dend, start + 7u), wend);
+                R.init(C.heap, h0, incl - lsum);
+                uint32_t d = start, rem = lsum;
+                while (rem && d < hend) {
+                    const uint32_t cd = R.peek4() & 0xFFu;
+                    uint32_t L = len[cd];
+                    uint64_t v = sym[cd];
+                    if (cd == 255u && rem > 1) {
+                        R.advance(1);
+                        --rem;
+                        v = R.peek4() & 0xFFu;
+                        L = 1;
+                    }
+                    for (uint32_t b = 0; b < L && d + b < hend; ++b) stage[d + b - w0] = (uint8_t)(v >> (8 * b));
+                    d += L;
+                    --rem;
+                    R.advance(1);
+                }
+            }
+            wave_lds_sync();
+            // copy-out: bytes up to a 4-byte boundary of the destination,
+            // then whole dwords (two aligned LDS dwords realigned), then the
+            // tail
             uint8_t* dst = bytes + d0 + w0;
-            for (uint32_t i = lane; i < wn; i += kWave) dst[i] = stage[i];
+            const uint32_t head = min(wn, (uint32_t)((4u - ((uintptr_t)dst & 3u)) & 3u));
+            if ((uint32_t)lane < head) dst[lane] = stage[lane];
+            const uint32_t nd = (wn - head) >> 2;
+            uint32_t* dw = reinterpret_cast<uint32_t*>(dst + head);
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(stage);
+            for (uint32_t i = lane; i < nd; i += kWave) {
+                const uint32_t so = head + 4u * i;
+                dw[i] = __builtin_amdgcn_alignbyte(sw[(so >> 2) + 1], sw[so >> 2], so & 3u);
+            }
+            for (uint32_t i = head + 4u * nd + lane; i < wn; i += kWave) dst[i] = stage[i];
             wave_lds_sync();
         }
     }
