@@ -216,3 +216,24 @@ def test_pruned_chunks_and_graph_replay(ctx):
     del g
     for p in plans:
         p.release()
+
+
+def test_tiny_records(ctx):
+    """Runs of empty and 1-3 byte strings between longer ones, so that a
+    lane's four rows hold fewer bytes than one symbol write spans and the
+    record decode's spill reaches past the next lane; a three-letter
+    alphabet makes the predicate depend on nearly every decoded byte."""
+    G.say("fsst tiny records")
+    rng = np.random.default_rng(77)
+    alpha = np.frombuffer(b"xyz", np.uint8)
+    n = 50_000
+    lens = rng.choice(np.array([0, 0, 1, 2, 3, 1, 0, 30]), n)
+    items = [bytes(rng.choice(alpha, int(k))) for k in lens]
+    t = {"s": to_strings(items), "g": (np.arange(n) % 7).astype(np.int32)}
+    db = G.make_db(ctx, {"t": t}, {"t": {"s": "FSST"}}, chunk_rows=4096)
+    for a, b in ((b"x", b"y"), (b"z", b"z"), (b"xy", b"x"), (b"y", b"xz")):
+        spec = {"fact": "t", "filters": [{"col": "s", "op": "STR_CONTAINS_SEQ", "s1": a, "s2": b}],
+                "probes": [], "group_by": [{"col": "g"}], "aggs": [{"op": "COUNT"}]}
+        want = oracle.run(spec, {"t": t})
+        for mode in ("FUSED", "FRAGMENTED"):
+            G.assert_same(G.run_gpu(db, spec, mode=mode), want, f"{a}/{b} {mode}")
