@@ -801,6 +801,18 @@ struct CodeReader {
         const uint32_t hi = __builtin_amdgcn_alignbyte(b0, a1, o & 3u);
         return (o & 4u) ? hi : lo;
     }
+    // the next 16 code bytes, four per word (a: the first four)
+    __device__ __forceinline__ void peek16(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) const {
+        const uint32_t o = pos - A;
+        const bool half = (o & 8u) != 0, q = (o & 4u) != 0;
+        const uint32_t B0 = half ? x.z : x.x, B1 = half ? x.w : x.y, B2 = half ? y.x : x.z, B3 = half ? y.y : x.w;
+        const uint32_t B4 = half ? y.z : y.x, B5 = half ? y.w : y.y;
+        const uint32_t c0 = q ? B1 : B0, c1 = q ? B2 : B1, c2 = q ? B3 : B2, c3 = q ? B4 : B3, c4 = q ? B5 : B4;
+        a = __builtin_amdgcn_alignbyte(c1, c0, o & 3u);
+        b = __builtin_amdgcn_alignbyte(c2, c1, o & 3u);
+        c = __builtin_amdgcn_alignbyte(c3, c2, o & 3u);
+        d = __builtin_amdgcn_alignbyte(c4, c3, o & 3u);
+    }
     // the next 8 code bytes (a: the first four)
     __device__ __forceinline__ void peek8(uint32_t& a, uint32_t& b) const {
         const uint32_t o = pos - A;
@@ -849,7 +861,7 @@ __device__ __forceinline__ bool fsst_lengths(CC& c, int m, int lane, int nvalid,
 // The string atom on FSST mini block m: returns the mask of rows that
 // contain s1 and, after its leftmost end, s2 (row 64 k + lane -> bit k).
 // Lane l takes rows 4 l .. 4 l + 3, whose codes are contiguous in the heap,
-// four codes per step.  fl: 256 bytes of the wave's LDS for the
+// sixteen codes per step.  fl: 256 bytes of the wave's LDS for the
 // transposition.
 __device__ __forceinline__ uint32_t fsst_pred(CQ& Q, CC& c, int m, int lane, int nvalid, uint8_t* fl,
                                               const uint8_t* smem_shared, bool& ok) {
@@ -870,20 +882,36 @@ __device__ __forceinline__ uint32_t fsst_pred(CQ& Q, CC& c, int m, int lane, int
         uint32_t rem = r == 0 ? rl[0] : r == 1 ? rl[1] : r == 2 ? rl[2] : rl[3];
         uint32_t st = 0;
         while (rem) {
-            const uint32_t q = R.peek4();
-            const uint32_t nq = min(rem, 4u);
-            // the states after 1, 2, 3 and 4 codes; the record may end first
-            const uint32_t s1 = T[__builtin_amdgcn_perm(st, q, 0x0c0c0400u)];
-            const uint32_t s2 = T[__builtin_amdgcn_perm(s1, q, 0x0c0c0401u)];
-            const uint32_t s3 = T[__builtin_amdgcn_perm(s2, q, 0x0c0c0402u)];
-            uint32_t s4 = T[__builtin_amdgcn_perm(s3, q, 0x0c0c0403u)];
-            // (an empty use keeps the fourth read unconditional: the compiler
-            // otherwise branches on nq around it)
-            asm volatile("" : "+v"(s4));
-            st = s1;
-            st = nq >= 2 ? s2 : st;
-            st = nq >= 3 ? s3 : st;
-            st = nq >= 4 ? s4 : st;
+            // sixteen codes a step (most records take one or two): the
+            // states after 1 .. 16 codes, then the one after nq of them
+            uint32_t qa, qb, qc, qd;
+            R.peek16(qa, qb, qc, qd);
+            const uint32_t nq = min(rem, 16u);
+            auto step = [&](uint32_t s, uint32_t w, uint32_t sel) -> uint32_t {
+                return T[__builtin_amdgcn_perm(s, w, sel)];
+            };
+            const uint32_t x0 = step(st, qa, 0x0c0c0400u), x1 = step(x0, qa, 0x0c0c0401u);
+            const uint32_t x2 = step(x1, qa, 0x0c0c0402u), x3 = step(x2, qa, 0x0c0c0403u);
+            const uint32_t x4 = step(x3, qb, 0x0c0c0400u), x5 = step(x4, qb, 0x0c0c0401u);
+            const uint32_t x6 = step(x5, qb, 0x0c0c0402u), x7 = step(x6, qb, 0x0c0c0403u);
+            const uint32_t x8 = step(x7, qc, 0x0c0c0400u), x9 = step(x8, qc, 0x0c0c0401u);
+            const uint32_t x10 = step(x9, qc, 0x0c0c0402u), x11 = step(x10, qc, 0x0c0c0403u);
+            const uint32_t x12 = step(x11, qd, 0x0c0c0400u), x13 = step(x12, qd, 0x0c0c0401u);
+            const uint32_t x14 = step(x13, qd, 0x0c0c0402u);
+            uint32_t x15 = step(x14, qd, 0x0c0c0403u);
+            // (an empty use keeps the last reads unconditional: the compiler
+            // otherwise branches on nq around them)
+            asm volatile("" : "+v"(x15));
+            {
+                // a select tree on the bits of nq - 1
+                const uint32_t i = nq - 1u;
+                const bool b0 = (i & 1u) != 0, b1 = (i & 2u) != 0, b2 = (i & 4u) != 0, b3 = (i & 8u) != 0;
+                const uint32_t t0 = b0 ? x1 : x0, t1 = b0 ? x3 : x2, t2 = b0 ? x5 : x4, t3 = b0 ? x7 : x6;
+                const uint32_t t4 = b0 ? x9 : x8, t5 = b0 ? x11 : x10, t6 = b0 ? x13 : x12, t7 = b0 ? x15 : x14;
+                const uint32_t u0 = b1 ? t1 : t0, u1 = b1 ? t3 : t2, u2 = b1 ? t5 : t4, u3 = b1 ? t7 : t6;
+                const uint32_t v0 = b2 ? u1 : u0, v1 = b2 ? u3 : u2;
+                st = b3 ? v1 : v0;
+            }
             // matched: the rest of the record is skipped
             const uint32_t adv = st == acc ? rem : nq;
             rem -= adv;
