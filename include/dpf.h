@@ -313,8 +313,14 @@ typedef struct {
 
 /* Validates the plan, proves every aggregate stays within int64 over the
  * table (else DPF_ERR_OVERFLOW), sizes the group table and pre-allocates the
- * per-plan device workspace and pinned result buffer, so that executing the
- * plan allocates nothing and can be captured in a HIP graph.  The device
+ * per-plan device workspace and pinned result buffer (paper Section 3.1,
+ * Kernels #3 and #4).  The group table is indexed by the group keys'
+ * combined value range (the product of each key's max - min + 1): directly
+ * up to 2^22 slots; above that it is an open-addressing hash table in
+ * device memory whose slot count is a power of two at least twice
+ * min(range, table rows), at most 2^27 slots (else DPF_ERR_UNSUPPORTED, as
+ * for a range above 2^62).  Executing the plan then allocates nothing and
+ * can be captured in a HIP graph.  The device
  * copy of the plan (its descriptor, the surviving-block list and the zeroed
  * workspace) is enqueued on the context's own upload stream from pinned
  * staging, and the call returns without waiting for it: every execution
@@ -381,8 +387,9 @@ dpf_status dpf_execute(dpf_ctx ctx, int32_t n, const dpf_plan* plans, const dpf_
  * until the process ends).  The call allocates no device or pinned memory
  * and creates no event.  mode must be DPF_MODE_FUSED (else
  * DPF_ERR_UNSUPPORTED).  The scratch needed is 2,304 bytes of counters plus,
- * per plan, 256 bytes of status and ngroups x accumulators x 8 bytes of
- * group table, each rounded up to 256 bytes; a batch needing more than
+ * per plan, 256 bytes of status and the group table (slots x accumulators
+ * x 8 bytes, plus slots x 8 bytes of keys for a hash table), each rounded up
+ * to 256 bytes; a batch needing more than
  * 8 MiB is refused with DPF_ERR_UNSUPPORTED before anything is enqueued.  The
  * call zeroes the part of the array it uses on the stream before its launch
  * (the array keeps the previous call's contents).  Every call on one GPU

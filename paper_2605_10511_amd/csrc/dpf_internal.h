@@ -25,6 +25,8 @@ constexpr int kMaxBatch = 64;     // plans per fused launch
 constexpr int kMaxHashCols = 8;   // dimension columns per hash build
 constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
 constexpr int64_t kMaxGroups = int64_t(1) << 22;  // direct-indexed group table limit
+constexpr int64_t kMaxHashSlots = int64_t(1) << 27;  // hash group table limit (slots)
+constexpr int64_t kMaxGroupDomain = int64_t(1) << 62;  // group index + 1 fits int64
 constexpr int32_t kEmptyKey = INT32_MIN;
 constexpr int kXcds = 8;             // XCDs per device; workgroup i is dispatched to XCD i % 8
 constexpr int kCounterStride = 32;   // 32-bit words between work-queue counters (128-byte lines)
@@ -156,12 +158,20 @@ struct DevQuery {
     int32_t nacc;    // accumulator 0 is the row count
     DevKey keys[kMaxKeys];
     DevAcc accs[kMaxAccs];
+    // Group table: ngroups rows of nacc accumulators, zero between
+    // executions.  Direct (agg_hash 0): row g is group index g.  Hash
+    // (agg_hash 1, a group-key domain above kMaxGroups): ngroups is a power
+    // of two at least twice the groups the table can receive, and ngroups
+    // keys follow the accumulators (group index + 1; 0: empty slot), placed
+    // by linear probing.
     int64_t ngroups;
-    int64_t* agg;        // device [ngroups * nacc], zero between executions
+    int64_t* agg;
     int32_t agg_lds;     // accumulate in the workgroup's LDS table first
     int32_t agg_lds_off; // byte offset of that table
     int32_t lds_shared;  // LDS bytes of this plan's shared area (hashes + table)
     int32_t has_str;
+    int32_t agg_hash;
+    int32_t agg_pad;
     // The string atom on an FSST column (index into preds, -1: none): its
     // byte automaton (fs_states rows of 256 next states, device memory) and
     // the byte offset of its code table ((2 fs_states + 1) rows of 256) in
@@ -181,9 +191,15 @@ struct DevQuery {
     int32_t prune_mb;
 };
 
+// Bytes of a plan's group table: the accumulators, and the keys of a hash
+// table.
+inline size_t agg_table_bytes(const DevQuery& q) {
+    return (size_t)q.ngroups * (size_t)(q.nacc + (q.agg_hash ? 1 : 0)) * 8;
+}
+
 struct BatchArgs {
     const DevQuery* q[kMaxBatch];
-    // Per plan: its group table ([ngroups * nacc] int64, zero between
+    // Per plan: its group table (agg_table_bytes, zero between
     // executions) and its status word, in the plan's workspace or in the
     // library's static scratch area.
     int64_t* agg[kMaxBatch];

@@ -1093,15 +1093,42 @@ __device__ __forceinline__ int64_t acc_value(CA& A, const S& sv) {
     return prod;
 }
 
+// Row of group g in the group table T: g itself (direct table), or the
+// slot that g holds in the hash table, claimed with a compare-and-swap on
+// the first free slot of its linear probe sequence (-1: no slot free, which
+// the table's size rules out).
+__device__ __forceinline__ int64_t agg_row(CQ& Q, unsigned long long* T, int64_t g) {
+    if (!Q.agg_hash) return g;
+    const uint64_t n = (uint64_t)Q.ngroups, mask = n - 1;
+    unsigned long long* K = T + n * (uint64_t)Q.nacc;
+    const unsigned long long key = (unsigned long long)g + 1ull;
+    uint64_t h = ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> 17;
+    for (uint64_t t = 0; t < n; ++t) {
+        h &= mask;
+        unsigned long long k = __hip_atomic_load(&K[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == 0ull) k = atomicCAS(&K[h], 0ull, key);
+        if (k == 0ull || k == key) return (int64_t)h;
+        ++h;
+    }
+    return -1;
+}
+
+// false: the hash group table had no free slot
 template <class S>
-__device__ __forceinline__ void aggregate_row(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const S& sv,
+__device__ __forceinline__ bool aggregate_row(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const S& sv,
                                               int64_t g) {
     const int nacc = Q.nacc;
-    unsigned long long* T = Q.agg_lds
-        ? reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc
-        : gagg + g * nacc;
+    unsigned long long* T;
+    if (Q.agg_lds) {
+        T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc;
+    } else {
+        const int64_t r = agg_row(Q, gagg, g);
+        if (r < 0) return false;
+        T = gagg + r * nacc;
+    }
     atomicAdd(&T[0], 1ull);
     for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,7 +1225,7 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, unsigned lo
     }
     int64_t g;
     if (!group_index(Q, sv, g)) { ok_hdr = false; return; }
-    aggregate_row(Q, smem_shared, gagg, sv, g);
+    if (!aggregate_row(Q, smem_shared, gagg, sv, g)) ok_hdr = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -1465,20 +1492,27 @@ __device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p
 
 // Write a plan's non-empty groups as records [group, acc...] into its pinned
 // host buffer (paper Section 3.1: the aggregate is converted into a record
-// format and returned to the host), then clear the device table T and the
-// status word for the next execution.  Run by one workgroup after every
-// other one has finished.
+// format and returned to the host), then clear the device table T (and a
+// hash table's keys) and the status word for the next execution.  Run by
+// one workgroup after every other one has finished.
 __device__ void emit_records(CQ& Q, int32_t* ctrl, unsigned long long* T, uint32_t* status) {
     const int nacc = Q.nacc;
     const int64_t G = Q.ngroups;
+    unsigned long long* K = Q.agg_hash ? T + G * nacc : nullptr;
     if (threadIdx.x == 0) ctrl[2] = 0;
     __syncthreads();
     for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
+        unsigned long long key = 0;
+        if (K) {
+            key = ld_acq(&K[g]);
+            if (key == 0) continue;
+            K[g] = 0;
+        }
         unsigned long long cnt = ld_acq(&T[g * nacc]);
         if (cnt == 0) continue;
         int pos = atomicAdd(&ctrl[2], 1);
         int64_t* rec = Q.host_out + 2 + (int64_t)pos * (1 + nacc);
-        rec[0] = g;
+        rec[0] = K ? (int64_t)(key - 1ull) : g;
         rec[1] = (int64_t)cnt;
         T[g * nacc] = 0;
         for (int a = 1; a < nacc; ++a) {
@@ -2266,7 +2300,7 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
     __shared__ unsigned long long tab[4096];
     CQ& Q = *ro(q);
     const int64_t n = (int64_t)*nrows_list;
-    const bool local = Q.ngroups * Q.nacc <= 4096;
+    const bool local = !Q.agg_hash && Q.ngroups * Q.nacc <= 4096;
     if (local)
         for (int e = threadIdx.x; e < Q.ngroups * Q.nacc; e += blockDim.x) tab[e] = 0;
     __syncthreads();
@@ -2291,7 +2325,15 @@ __global__ __launch_bounds__(kBlock) void frag_aggregate(const DevQuery* __restr
         }
         int64_t g;
         if (!group_index(Q, sv, g)) { okall = false; continue; }
-        unsigned long long* T = local ? &tab[g * Q.nacc] : reinterpret_cast<unsigned long long*>(Q.agg) + g * Q.nacc;
+        unsigned long long* T;
+        if (local) {
+            T = &tab[g * Q.nacc];
+        } else {
+            unsigned long long* A = reinterpret_cast<unsigned long long*>(Q.agg);
+            const int64_t row = agg_row(Q, A, g);
+            if (row < 0) { okall = false; continue; }
+            T = A + row * Q.nacc;
+        }
         atomicAdd(&T[0], 1ull);
         for (int a = 1; a < Q.nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
     }

@@ -967,7 +967,7 @@ void assign_lds(dpf_plan p, int32_t budget) {
         off += (int32_t)align_up((size_t)b, 16);
     }
     const int64_t aggb = q.ngroups * q.nacc * 8;
-    q.agg_lds = aggb <= kAggLdsMax;
+    q.agg_lds = !q.agg_hash && aggb <= kAggLdsMax;
     q.agg_lds_off = off;
     if (q.agg_lds) off += (int32_t)align_up((size_t)aggb, 16);
     q.lds_shared = off;
@@ -1184,7 +1184,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         p->keys[k].card = q.keys[k].card;
         p->keys[k].dict = dict;
         G *= card;
-        if (G > kMaxGroups) return bail(fail(DPF_ERR_UNSUPPORTED, "group-key domain exceeds 2^22 slots"));
+        if (G > kMaxGroupDomain) return bail(fail(DPF_ERR_UNSUPPORTED, "group-key domain exceeds 2^62"));
     }
     int64_t stride = 1;
     for (int k = desc->nkeys - 1; k >= 0; --k) {
@@ -1192,7 +1192,21 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         p->keys[k].stride = stride;
         stride *= q.keys[k].card;
     }
-    q.ngroups = (int64_t)G;
+    // A domain above kMaxGroups aggregates through a hash table (paper
+    // Section 3.1, Kernel #3): at least twice as many slots as the groups
+    // that can occur (no more than the domain, nor than the table's rows).
+    q.agg_hash = G > kMaxGroups;
+    if (q.agg_hash) {
+        const int64_t can = std::min<int64_t>((int64_t)G, std::max<int64_t>(nrows, 1));
+        int64_t slots = 64;
+        while (slots < 2 * can) slots *= 2;
+        if (slots > kMaxHashSlots)
+            return bail(fail(DPF_ERR_UNSUPPORTED, "a hash group table above 2^27 slots (a group-key domain above "
+                                                  "2^22 over more than 2^26 rows)"));
+        q.ngroups = slots;
+    } else {
+        q.ngroups = (int64_t)G;
+    }
 
     // accumulators: 0 = count, then one per SUM/AVG; int64 bound proof
     q.nacc = 1;
@@ -1268,7 +1282,7 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
     // device memory: [DevQuery][agg table][status][counters][live blocks]
     // [FSST byte automaton]
     const size_t q_off = 0, agg_off = align_up(sizeof(DevQuery), 256);
-    const size_t agg_bytes = (size_t)q.ngroups * q.nacc * 8;
+    const size_t agg_bytes = agg_table_bytes(q);
     const size_t st_off = align_up(agg_off + agg_bytes, 256), cnt_off = st_off + 256;
     const size_t live_off = align_up(cnt_off + (size_t)kCounterWords * 4, 256);
     const size_t dfa_off = align_up(live_off + live.size() * 4, 256);
@@ -1653,7 +1667,7 @@ extern "C" dpf_status dpf_execute_noalloc(dpf_ctx ctx, int32_t n, const dpf_plan
     ws.counters = (uint32_t*)ctx->scratch;
     for (int i = 0; i < n; ++i) {
         const DevQuery& q = plans[i]->hq;
-        const size_t agg_bytes = (size_t)q.ngroups * (size_t)q.nacc * 8;
+        const size_t agg_bytes = agg_table_bytes(q);
         if (agg_bytes > kStaticScratchBytes) off = kStaticScratchBytes + 1;
         if (off > kStaticScratchBytes) break;
         ws.status[i] = (uint32_t*)(ctx->scratch + off);
