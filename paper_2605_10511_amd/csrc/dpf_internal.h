@@ -212,6 +212,7 @@ struct BatchArgs {
     int32_t lds_shared;   // max lds_shared over the batch
     int32_t str_stage;    // per-wave string staging present (2: some plan has an FSST atom)
     int32_t pend_stage;   // per-wave survivor queue present (some plan has a fact predicate or a probe)
+    int32_t agg_hash;     // some plan aggregates into a hash group table
 };
 
 // Hash build over a dimension table (optionally joined: the rows must find

@@ -1113,18 +1113,21 @@ __device__ __forceinline__ int64_t agg_row(CQ& Q, unsigned long long* T, int64_t
     return -1;
 }
 
-// false: the hash group table had no free slot
-template <class S>
+// false: the hash group table had no free slot.  kHash: the batch has a
+// plan with a hash group table (only those instantiations carry its code).
+template <bool kHash, class S>
 __device__ __forceinline__ bool aggregate_row(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const S& sv,
                                               int64_t g) {
     const int nacc = Q.nacc;
-    unsigned long long* T;
-    if (Q.agg_lds) {
-        T = reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc;
-    } else {
-        const int64_t r = agg_row(Q, gagg, g);
-        if (r < 0) return false;
-        T = gagg + r * nacc;
+    unsigned long long* T = Q.agg_lds
+        ? reinterpret_cast<unsigned long long*>(smem_shared + Q.agg_lds_off) + g * nacc
+        : gagg + g * nacc;
+    if constexpr (kHash) {
+        if (Q.agg_hash) {
+            const int64_t r = agg_row(Q, gagg, g);
+            if (r < 0) return false;
+            T = gagg + r * nacc;
+        }
     }
     atomicAdd(&T[0], 1ull);
     for (int a = 1; a < nacc; ++a) atomicAdd(&T[a], (unsigned long long)acc_value(Q.accs[a], sv));
@@ -1136,6 +1139,7 @@ __device__ __forceinline__ bool aggregate_row(CQ& Q, uint8_t* smem_shared, unsig
 // may differ between lanes (rows queued from several mini blocks).  gagg is
 // the plan's group table in device memory.
 // ---------------------------------------------------------------------------
+template <bool kHash>
 __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, LdsSlots sv, int m,
                                         int i, bool active, bool& ok_hdr) {
     bool ok = active;
@@ -1225,7 +1229,7 @@ __device__ __forceinline__ void stage_b(CQ& Q, uint8_t* smem_shared, unsigned lo
     }
     int64_t g;
     if (!group_index(Q, sv, g)) { ok_hdr = false; return; }
-    if (!aggregate_row(Q, smem_shared, gagg, sv, g)) ok_hdr = false;
+    if (!aggregate_row<kHash>(Q, smem_shared, gagg, sv, g)) ok_hdr = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -1241,6 +1245,7 @@ struct WaveArea {
     uint4* recs;       // [kRecCap] string words with a prefix hit
 };
 
+template <bool kHash>
 __device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                               int& npend, int lane, bool& ok_hdr) {
     wave_lds_sync();
@@ -1248,12 +1253,14 @@ __device__ __forceinline__ void flush_pending(CQ& Q, uint8_t* smem_shared, unsig
         int idx = base + lane;
         bool act = idx < npend;
         uint32_t row = W.pend[act ? idx : 0];
-        stage_b(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, (int)(row >> 8), (int)(row & 255u), act, ok_hdr);
+        stage_b<kHash>(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, (int)(row >> 8), (int)(row & 255u), act,
+                       ok_hdr);
     }
     npend = 0;
     wave_lds_sync();
 }
 
+template <bool kHash>
 __device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                                 int64_t row0, uint32_t mask, int lane, int& npend, bool& ok_hdr) {
     if (__ballot(mask != 0) == 0) return;
@@ -1265,7 +1272,7 @@ __device__ __forceinline__ void queue_survivors(CQ& Q, uint8_t* smem_shared, uns
         if (bit) W.pend[npend + bits_below(b)] = (uint32_t)(row0 + 64 * k + lane);
         npend += (int)__popcll(b);
     }
-    if (npend >= kWave) flush_pending(Q, smem_shared, gagg, W, npend, lane, ok_hdr);
+    if (npend >= kWave) flush_pending<kHash>(Q, smem_shared, gagg, W, npend, lane, ok_hdr);
 }
 
 // Stage A of mini block m: returns the mask of rows passing every atom (row
@@ -1340,7 +1347,7 @@ __device__ __forceinline__ uint32_t member_tile(CQ& Q, const uint8_t* smem_share
                              : hash_member4<false>(P0.h, smem_shared, fk, mask);
 }
 
-template <int kStr>
+template <int kStr, bool kHash>
 __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                              int m, int lane, int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
@@ -1353,7 +1360,7 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsign
         for (int k = 0; k < 4; ++k) {
             if (64 * k >= nvalid) break;
             int i = 64 * k + lane;
-            stage_b(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, m, i, i < nvalid, ok_hdr);
+            stage_b<kHash>(Q, smem_shared, gagg, LdsSlots{W.slots + lane}, m, i, i < nvalid, ok_hdr);
         }
         return;
     }
@@ -1368,12 +1375,13 @@ __device__ __forceinline__ void process_tile(CQ& Q, uint8_t* smem_shared, unsign
     // loads, so stage B gets only the rows that find their key (and probes
     // them again for payloads), not every row that passed the filters.
     if (Q.nprobes > 0 && __ballot(mask != 0)) mask = member_tile(Q, smem_shared, m, lane, mask, ok_hdr);
-    queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
+    queue_survivors<kHash>(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
 // Semi-join stage A of one mini block whose foreign keys issue_dense read:
 // the first (most selective) probe filters; its survivors are probed again,
 // with payloads, in stage B.
+template <bool kHash>
 __device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                           int m, int lane, const RawDense& R, int& npend, bool& ok_hdr) {
     const int64_t row0 = (int64_t)m * kMB;
@@ -1390,12 +1398,12 @@ __device__ __forceinline__ void semi_tile(CQ& Q, uint8_t* smem_shared, unsigned 
         for (int k = 0; k < 4; ++k) fk[k] = (mask >> k) & 1u ? dict_value(fc, fk[k], ok_hdr) : 0;
     mask = P0.h.lds_off >= 0 ? hash_member4<true>(P0.h, smem_shared, fk, mask)
                              : hash_member4<false>(P0.h, smem_shared, fk, mask);
-    queue_survivors(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
+    queue_survivors<kHash>(Q, smem_shared, gagg, W, row0, mask, lane, npend, ok_hdr);
 }
 
 // The semi-join tiles m0, m0 + NW, ... < m1 of one wave, two in flight: the
 // next tile's keys are loaded while the current one is probed.
-template <int NW>
+template <int NW, bool kHash>
 __device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, unsigned long long* gagg, const WaveArea& W,
                                            int m0, int m1, int lane, int& npend, bool& ok_hdr) {
     CC& fc = Q.cols[Q.probes[0].fk_col];
@@ -1405,11 +1413,11 @@ __device__ __forceinline__ void semi_tiles(CQ& Q, uint8_t* smem_shared, unsigned
         const int m2 = m + NW;
         dense_ready(A);  // as seg_ready: wait for A before B's loads are issued
         if (m2 < m1) issue_dense(fc, m2, lane, B);
-        semi_tile(Q, smem_shared, gagg, W, m, lane, A, npend, ok_hdr);
+        semi_tile<kHash>(Q, smem_shared, gagg, W, m, lane, A, npend, ok_hdr);
         if (m2 >= m1) break;
         dense_ready(B);
         if (m2 + NW < m1) issue_dense(fc, m2 + NW, lane, A);
-        semi_tile(Q, smem_shared, gagg, W, m2, lane, B, npend, ok_hdr);
+        semi_tile<kHash>(Q, smem_shared, gagg, W, m2, lane, B, npend, ok_hdr);
     }
 }
 
@@ -1571,8 +1579,8 @@ __device__ __forceinline__ bool finish_last(const BatchArgs& a, int home) {
 // The persistent fused kernel (NW waves per workgroup)
 // ---------------------------------------------------------------------------
 // kStr: 0 no string atom in the batch, 1 string atoms on VARLEN columns, 2
-// also an FSST atom.
-template <int NW, int kStr>
+// also an FSST atom.  kHash: some plan aggregates into a hash group table.
+template <int NW, int kStr, bool kHash>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr == 2 ? 5 : kStr ? 6 : 4, 8))) void fused_kernel(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // Static LDS: its address is known when the kernel is compiled, so the
@@ -1619,7 +1627,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
                 // item keeps the workgroup's other waves waiting at the next
                 // item's barrier (measured: without string atoms, deferring
                 // is faster; with them, flushing per item).
-                if (npend) flush_pending(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
+                if (npend) flush_pending<kHash>(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
                 __syncthreads();
                 sink += flush_lds_agg(*ro(a.q[cur]), shared_area, cagg);
                 if (!ok_hdr) sink += atomicOr(a.status[cur], ST_CORRUPT);
@@ -1648,7 +1656,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
             mb1 = min(mb0 + a.mb_per_item, Q.nmb);
         }
         if (Q.npreds == 0 && Q.nprobes > 0) {
-            semi_tiles<NW>(Q, shared_area, gagg, W, mb0 + wave, mb1, lane, npend, ok_hdr);
+            semi_tiles<NW, kHash>(Q, shared_area, gagg, W, mb0 + wave, mb1, lane, npend, ok_hdr);
         } else if (kStr == 2 && Q.fs_pred >= 0) {
             // FSST: the item's mini blocks chunk by chunk, each chunk's code
             // tables built once by the workgroup
@@ -1663,18 +1671,18 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(kStr
                     fs_chunk = k;
                 }
                 for (int m = s0 + wave; m < s1; m += NW)
-                    process_tile<kStr>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
+                    process_tile<kStr, kHash>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
                 s0 = s1;
             }
         } else {
             for (int m = mb0 + wave; m < mb1; m += NW)
-                process_tile<kStr>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
+                process_tile<kStr, kHash>(Q, shared_area, gagg, W, m, lane, npend, ok_hdr);
         }
-        if (kStr && npend) flush_pending(Q, shared_area, gagg, W, npend, lane, ok_hdr);
+        if (kStr && npend) flush_pending<kHash>(Q, shared_area, gagg, W, npend, lane, ok_hdr);
     }
     if (cur >= 0) {
         unsigned long long* const cagg = reinterpret_cast<unsigned long long*>(a.agg[cur]);
-        if (npend) flush_pending(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
+        if (npend) flush_pending<kHash>(*ro(a.q[cur]), shared_area, cagg, W, npend, lane, ok_hdr);
         __syncthreads();
         sink += flush_lds_agg(*ro(a.q[cur]), shared_area, cagg);
         if (!ok_hdr) sink += atomicOr(a.status[cur], ST_CORRUPT);
@@ -2356,20 +2364,28 @@ __global__ void frag_reset_counts(unsigned long long* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-// Three instantiations per workgroup size: only batches with a string atom
+// Six instantiations per workgroup size: only batches with a string atom
 // carry the string stage's code and registers (its segment buffers and
 // record queue), and only those with an FSST atom the FSST walk; the plain
-// instantiation is smaller and spills nothing.
-template <int NW, int kStr>
-hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
+// instantiation is smaller and spills nothing.  Only batches with a hash
+// group table carry its probing code in stage B (its mere presence there
+// slowed the star join by 3%).
+template <int NW, int kStr, bool kHash>
+hipError_t launch_fused_nwh(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW, kStr>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<NW, kStr, kHash>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)kLdsStrTabBytes);
         attr_set = true;
     }
-    hipLaunchKernelGGL((fused_kernel<NW, kStr>), dim3(grid), dim3(NW * kWave), lds_bytes, s, a);
+    hipLaunchKernelGGL((fused_kernel<NW, kStr, kHash>), dim3(grid), dim3(NW * kWave), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+template <int NW, int kStr>
+hipError_t launch_fused_nw(const BatchArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
+    return a.agg_hash ? launch_fused_nwh<NW, kStr, true>(a, grid, lds_bytes, s)
+                      : launch_fused_nwh<NW, kStr, false>(a, grid, lds_bytes, s);
 }
 
 }  // namespace

@@ -1521,6 +1521,7 @@ dpf_status launch_fused_batch(dpf_ctx ctx, int32_t n, const dpf_plan* plans, con
         str |= q.has_str != 0;
         fsst |= q.fs_pred >= 0;
         pend |= q.npreds > 0 || q.nprobes > 0;
+        a.agg_hash |= q.agg_hash;
         shared = std::max(shared, q.lds_shared);
         total_mb += q.live ? std::min<int64_t>(q.nmb, (int64_t)q.nlive * q.prune_mb) : q.nmb;
     }
