@@ -318,8 +318,9 @@ typedef struct {
  * combined value range (the product of each key's max - min + 1): directly
  * up to 2^22 slots; above that it is an open-addressing hash table in
  * device memory whose slot count is a power of two at least twice
- * min(range, table rows), at most 2^27 slots (else DPF_ERR_UNSUPPORTED, as
- * for a range above 2^62).  Executing the plan then allocates nothing and
+ * min(range, table rows), at most 2^22 slots, as the direct table (else
+ * DPF_ERR_UNSUPPORTED, as for a range above 2^62): the workgroup that
+ * finishes last scans the table to emit the records.  Executing the plan then allocates nothing and
  * can be captured in a HIP graph.  The device
  * copy of the plan (its descriptor, the surviving-block list and the zeroed
  * workspace) is enqueued on the context's own upload stream from pinned

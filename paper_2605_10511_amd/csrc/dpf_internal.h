@@ -25,7 +25,7 @@ constexpr int kMaxBatch = 64;     // plans per fused launch
 constexpr int kMaxHashCols = 8;   // dimension columns per hash build
 constexpr int kMaxHashPreds = 8;  // dimension predicates per hash build
 constexpr int64_t kMaxGroups = int64_t(1) << 22;  // direct-indexed group table limit
-constexpr int64_t kMaxHashSlots = int64_t(1) << 27;  // hash group table limit (slots)
+constexpr int64_t kMaxHashSlots = int64_t(1) << 22;  // hash group table limit (slots; one workgroup emits it)
 constexpr int64_t kMaxGroupDomain = int64_t(1) << 62;  // group index + 1 fits int64
 constexpr int32_t kEmptyKey = INT32_MIN;
 constexpr int kXcds = 8;             // XCDs per device; workgroup i is dispatched to XCD i % 8

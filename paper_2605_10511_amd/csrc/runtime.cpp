@@ -1201,8 +1201,8 @@ extern "C" dpf_status dpf_plan_build(dpf_ctx ctx, const dpf_plan_desc* desc, dpf
         int64_t slots = 64;
         while (slots < 2 * can) slots *= 2;
         if (slots > kMaxHashSlots)
-            return bail(fail(DPF_ERR_UNSUPPORTED, "a hash group table above 2^27 slots (a group-key domain above "
-                                                  "2^22 over more than 2^26 rows)"));
+            return bail(fail(DPF_ERR_UNSUPPORTED, "a hash group table above 2^22 slots (a group-key domain above "
+                                                  "2^22 over more than 2^21 rows)"));
         q.ngroups = slots;
     } else {
         q.ngroups = (int64_t)G;

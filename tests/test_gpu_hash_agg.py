@@ -125,7 +125,8 @@ def test_noalloc_twice(ctx):
 
 def test_domain_limits(ctx):
     """A domain above 2^62 (three 32-bit keys) is refused; one of 2^32 over
-    1,000 rows takes a 2,048-slot table."""
+    1,000 rows takes a 2,048-slot table; a hash table above 2^22 slots is
+    refused, and the same table still groups by a small key."""
     from paper_2605_10511_amd import dpf
     n = 1000
     rng = np.random.default_rng(3)
@@ -138,3 +139,9 @@ def test_domain_limits(ctx):
         db.plan(_spec(keys=("p", "q", "r")))
     spec = _spec(keys=("p", "b"), d_lt=1)
     G.assert_same(G.run_gpu(db, spec), oracle.run(spec, {"t": t}), "2^32 domain over 1000 rows")
+    # 2^21 + 1 rows under a 10^8 range would need 2^23 slots: refused
+    big = _table(2**21 + 1, seed=4)
+    dbb = G.make_db(ctx, {"t": big})
+    with pytest.raises(dpf.DpfError):
+        dbb.plan(_spec())
+    G.assert_same(G.run_gpu(dbb, _spec(keys=("b",))), oracle.run(_spec(keys=("b",)), {"t": big}), "direct table")
